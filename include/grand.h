@@ -1,0 +1,161 @@
+/*
+ * grand.h -- C ABI of the MI355X (gfx950) GRAND decoder for Gray M-QAM
+ * modulated polar codewords (arXiv 2405.01808).
+ *
+ * The decoder follows Algorithm 2 of Section III: per-symbol likelihoods and
+ * near-neighbour candidates (Definitions 3.1 and 3.2), test error patterns
+ * queried from most to least likely, the syndrome H (yhat + e)^T evaluated
+ * for each pattern (Algorithm 1 for the hard word, column updates for the
+ * patterns), stopping at the first zero syndrome.  The paper leaves the loop
+ * without an exit; this library abandons after a query cap, as GRAND-AB does
+ * (Section I), and reports the abandonment in a flag, not as an error.
+ *
+ * Conventions fixed by this library (the paper does not fix them):
+ *   - received coordinates are in odd-integer lattice units (Section II,
+ *     Definition "M-QAM": values divided by d of Eq. 2);
+ *   - each coordinate is quantised to round_half_even(4096 x); every cost is
+ *     an integer in units of 1/4096, saturated at 32767;
+ *   - Gray labels: binary reflected per axis, level 0 = most negative
+ *     amplitude, in-phase bits first, most significant bit first; bits of the
+ *     last symbol beyond N are pad bits and are never flipped;
+ *   - patterns are queried in ascending (sum of costs, colex order of item
+ *     ranks), items being ranked by (cost, bit position);
+ *   - the query count q is the 1-based rank of the accepted pattern in that
+ *     order (the hard word itself is query 1).
+ *
+ * All functions return GRAND_OK (0) or a negative error code.  On error the
+ * outputs are left untouched.  Functions may be called from several host
+ * threads; calls that share a stream are serialised by the caller.
+ */
+#ifndef GRAND_H
+#define GRAND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GRAND_OK = 0,
+    GRAND_EINVAL = -1,    /* bad argument (null pointer, size, M, cap, noise variance, rx value) */
+    GRAND_ENOMEM = -2,    /* host or device allocation failed */
+    GRAND_EDEVICE = -3,   /* a HIP runtime call failed; see grand_last_error() */
+    GRAND_EBUSY = -4,     /* server admission refused (memory budget or slot table full) */
+    GRAND_ECAPACITY = -5, /* a decode needed more device scratch than configured */
+    GRAND_ENOTFOUND = -6  /* server: no such request, or nothing completed */
+};
+
+/* Largest supported block length and query cap. */
+#define GRAND_MAX_N 1024u
+#define GRAND_MAX_CAP (1ull << 40)
+
+/* Human-readable text for an error code (static storage). */
+const char *grand_strerror(int err);
+
+/* Detail of the last error raised on the calling host thread ("" if none). */
+const char *grand_last_error(void);
+
+/* Select the HIP device used by this thread's subsequent calls and
+ * initialise the library on it.  Optional: every call initialises the
+ * current device on first use. */
+int grand_init(int device);
+
+/* ------------------------------------------------------------------ */
+/* Codes                                                               */
+/* ------------------------------------------------------------------ */
+
+typedef struct grand_code grand_code;
+
+/* Create a decoder handle for the code with parity-check matrix H
+ * (Definition "Polar codes", Section II: H is (N - K) x N with
+ * G_I H^T = 0; any matrix is accepted, the decoder only tests H x^T = 0).
+ *   n      block length N, a power of two, 2 <= n <= 1024;
+ *   rows   number of rows of H, 1 <= rows < n (rows <= 512);
+ *   h_rows host pointer, rows x ceil(n/64) uint64 words, row-major; bit j of
+ *          row i is bit (j % 64) of word i*ceil(n/64) + j/64.  Bits at
+ *          j >= n must be zero.
+ * The library copies H (row-packed for Algorithm 1 and column-packed for
+ * the pattern updates) to the current device; the caller keeps ownership of
+ * h_rows.  The handle is immutable and may be shared between threads. */
+int grand_code_create(uint32_t n, uint32_t rows, const uint64_t *h_rows,
+                      grand_code **out);
+void grand_code_destroy(grand_code *code);
+uint32_t grand_code_n(const grand_code *code);
+uint32_t grand_code_rows(const grand_code *code);
+
+/* ------------------------------------------------------------------ */
+/* One decode, host buffers, synchronous (Algorithm 2 for one word).   */
+/* ------------------------------------------------------------------ */
+
+/* rx         host pointer, 2L floats (a_1, b_1, a_2, b_2, ...), L =
+ *            ceil(n / log2 M); each finite with |x| <= 32768;
+ * M          4, 16, 64, 256, 1024 or 4096;
+ * noise_var  per-dimension noise variance in lattice units, finite and > 0.
+ *            It scales every penalty alike, so it cannot change the order
+ *            of the patterns; it is validated only;
+ * query_cap  1 <= cap <= GRAND_MAX_CAP;
+ * codeword_out host pointer, ceil(n/64) uint64 words (bit order as h_rows);
+ * queries_out, abandoned_out host pointers.
+ * On success with abandoned = 0 the codeword satisfies H x^T = 0 and q is
+ * the query count; with abandoned = 1 the hard-decision word is returned
+ * and q = min(cap, 2^(number of candidate flips)). */
+int grand_decode(const grand_code *code, const float *rx, uint32_t M,
+                 float noise_var, uint64_t query_cap, uint64_t *codeword_out,
+                 uint64_t *queries_out, uint8_t *abandoned_out);
+
+/* ------------------------------------------------------------------ */
+/* Many decodes, device buffers, asynchronous on a HIP stream.         */
+/* ------------------------------------------------------------------ */
+
+/* Per-codeword metadata lives in host memory (it drives the launch plan:
+ * codewords are grouped into (n, M) buckets, each with its own tuned launch
+ * shape); bulk data lives in device memory. */
+typedef struct {
+    uint32_t count;                /* number of codewords */
+    uint32_t n_codes;              /* entries in codes[] */
+    const grand_code *const *codes;/* host array of code handles */
+    const uint32_t *code_index;    /* host [count]: codes[code_index[i]] decodes word i */
+    const uint32_t *M;             /* host [count] */
+    const uint64_t *query_cap;     /* host [count] */
+    const float *noise_var;        /* host [count] (validated only) */
+    const uint64_t *rx_offset;     /* host [count]: float offset of word i's 2L values in rx */
+    const float *rx;               /* device */
+    uint64_t *codeword_out;        /* device [count * 16] uint64: word i at i*16, ceil(n/64) used */
+    uint64_t *queries_out;         /* device [count] */
+    uint8_t *abandoned_out;        /* device [count] */
+    int32_t *status_out;           /* device [count]: GRAND_OK, GRAND_EINVAL (bad rx values)
+                                      or GRAND_ECAPACITY; may be NULL */
+    uint64_t *checks_out;          /* device [count]: syndrome checks actually performed
+                                      (>= q; includes speculative checks); may be NULL */
+} grand_batch;
+
+/* Enqueue the decode of every codeword of the batch on `stream` (a
+ * hipStream_t; NULL = the default stream) and return.  Outputs are valid
+ * once the stream has completed.  Host-side validation errors are returned
+ * directly and nothing is enqueued. */
+int grand_decode_batch(const grand_batch *batch, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Launch-shape tuning                                                 */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t low_bits;     /* b: the b cheapest flips form the sorted low table (0..13) */
+    uint32_t block;        /* threads per workgroup (64..1024, multiple of 64) */
+    uint32_t seg_len;      /* low-table entries per check segment (1..256) */
+    uint32_t first_band;   /* patterns in the first cost band (>= 1) */
+    uint32_t node_cap;     /* high-pattern store per workgroup (entries) */
+    uint32_t grid_per_cu;  /* resident workgroups per compute unit for batches */
+} grand_tuning;
+
+/* Tuning used for codes of length n and modulation M (defaults are built
+ * in; grand_tuning_set overrides one (n, M) bucket, n = 0 or M = 0 acting as
+ * a wildcard). */
+int grand_tuning_get(uint32_t n, uint32_t M, grand_tuning *out);
+int grand_tuning_set(uint32_t n, uint32_t M, const grand_tuning *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

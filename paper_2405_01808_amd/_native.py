@@ -1,0 +1,94 @@
+"""ctypes declarations of the C ABI in include/grand.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrand.so")
+
+GRAND_OK = 0
+GRAND_EINVAL = -1
+GRAND_ENOMEM = -2
+GRAND_EDEVICE = -3
+GRAND_EBUSY = -4
+GRAND_ECAPACITY = -5
+GRAND_ENOTFOUND = -6
+GRAND_MAX_N = 1024
+GRAND_MAX_CAP = 1 << 40
+CW_STRIDE = 16   # uint64 words per codeword in batch outputs
+
+# Every symbol the header declares; tests check that the library exports them.
+EXPORTS = [
+    "grand_strerror", "grand_last_error", "grand_init",
+    "grand_code_create", "grand_code_destroy", "grand_code_n", "grand_code_rows",
+    "grand_decode", "grand_decode_batch", "grand_tuning_get", "grand_tuning_set",
+]
+
+
+class GrandTuning(ctypes.Structure):
+    _fields_ = [("low_bits", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("seg_len", ctypes.c_uint32), ("first_band", ctypes.c_uint32),
+                ("node_cap", ctypes.c_uint32), ("grid_per_cu", ctypes.c_uint32)]
+
+
+class GrandBatch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint32), ("n_codes", ctypes.c_uint32),
+                ("codes", ctypes.POINTER(ctypes.c_void_p)),
+                ("code_index", ctypes.c_void_p), ("M", ctypes.c_void_p),
+                ("query_cap", ctypes.c_void_p), ("noise_var", ctypes.c_void_p),
+                ("rx_offset", ctypes.c_void_p), ("rx", ctypes.c_void_p),
+                ("codeword_out", ctypes.c_void_p), ("queries_out", ctypes.c_void_p),
+                ("abandoned_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
+                ("checks_out", ctypes.c_void_p)]
+
+
+class GrandError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (error {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libgrand.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2405_01808_amd.build "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.grand_strerror.argtypes = [i32]
+    L.grand_strerror.restype = ctypes.c_char_p
+    L.grand_last_error.argtypes = []
+    L.grand_last_error.restype = ctypes.c_char_p
+    L.grand_init.argtypes = [i32]
+    L.grand_init.restype = i32
+    L.grand_code_create.argtypes = [u32, u32, vp, ctypes.POINTER(vp)]
+    L.grand_code_create.restype = i32
+    L.grand_code_destroy.argtypes = [vp]
+    L.grand_code_destroy.restype = None
+    L.grand_code_n.argtypes = [vp]
+    L.grand_code_n.restype = u32
+    L.grand_code_rows.argtypes = [vp]
+    L.grand_code_rows.restype = u32
+    L.grand_decode.argtypes = [vp, vp, u32, ctypes.c_float, u64, vp, vp, vp]
+    L.grand_decode.restype = i32
+    L.grand_decode_batch.argtypes = [ctypes.POINTER(GrandBatch), vp]
+    L.grand_decode_batch.restype = i32
+    L.grand_tuning_get.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]
+    L.grand_tuning_get.restype = i32
+    L.grand_tuning_set.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]
+    L.grand_tuning_set.restype = i32
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != GRAND_OK:
+        L = lib()
+        raise GrandError(rc, f"{L.grand_strerror(rc).decode()}: {L.grand_last_error().decode()}")

@@ -1,0 +1,559 @@
+// grand_api.hip -- host runtime behind include/grand.h: code handles, launch
+// planning (bucketing by (n, M) with per-bucket tuning), device scratch and
+// staging buffers, argument validation and error reporting.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "grand.h"
+#include "grand_internal.h"
+
+using namespace grand;
+
+struct grand_code {
+    uint32_t n, rows, kw, row_w32;
+    int device;
+    uint32_t *d_rows;   // rows x row_w32
+    uint32_t *d_cols;   // n x kw
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(GRAND_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool valid_m(uint32_t M)
+{
+    for (int m = 1; m <= 6; m++)
+        if (M == (1u << (2 * m)))
+            return true;
+    return false;
+}
+
+uint32_t bits_per_axis(uint32_t M)
+{
+    uint32_t m = 0;
+    while ((1u << (2 * (m + 1))) <= M)
+        m++;
+    return m;
+}
+
+uint32_t symbols(uint32_t n, uint32_t M)
+{
+    uint32_t m = bits_per_axis(M);
+    return (n + 2 * m - 1) / (2 * m);
+}
+
+// ---------------------------------------------------------------- tuning
+std::mutex g_tune_mu;
+std::map<std::pair<uint32_t, uint32_t>, grand_tuning> g_tune;
+
+grand_tuning builtin_tuning(uint32_t n, uint32_t M)
+{
+    (void)M;
+    grand_tuning t;
+    t.low_bits = n <= 64 ? 8 : 10;
+    t.block = 256;
+    t.seg_len = 32;
+    t.first_band = 256;
+    t.node_cap = 1u << 16;
+    t.grid_per_cu = 2;
+    return t;
+}
+
+grand_tuning tuning_for(uint32_t n, uint32_t M)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (auto key : {std::make_pair(n, M), std::make_pair(n, 0u), std::make_pair(0u, M),
+                     std::make_pair(0u, 0u)}) {
+        auto it = g_tune.find(key);
+        if (it != g_tune.end())
+            return it->second;
+    }
+    return builtin_tuning(n, M);
+}
+
+bool valid_tuning(const grand_tuning &t)
+{
+    return t.low_bits <= kMaxLowBits && t.block >= 64 && t.block <= kMaxBlock &&
+           t.block % 64 == 0 && t.seg_len >= 1 && t.seg_len <= 256 && t.first_band >= 1 &&
+           t.node_cap >= 64 && t.node_cap <= (1u << 22) && t.grid_per_cu >= 1 &&
+           t.grid_per_cu <= 32;
+}
+
+uint32_t seg_cap_for(const grand_tuning &t)
+{
+    uint32_t per = ((1u << t.low_bits) + t.seg_len - 1) / t.seg_len;
+    return t.block * per + t.block;
+}
+
+// ---------------------------------------------------------------- device context
+struct StreamRes {
+    uint8_t *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    uint32_t *queues = nullptr;     // 64 counters
+    DevJob *jobs = nullptr;
+    size_t jobs_cap = 0;
+    DevCode *codes = nullptr;
+    size_t codes_cap = 0;
+    DevJob *h_jobs = nullptr;       // pinned staging
+    size_t h_jobs_cap = 0;
+    DevCode *h_codes = nullptr;
+    size_t h_codes_cap = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    // single-decode buffers
+    float *d_rx = nullptr;
+    uint64_t *d_out = nullptr;      // 16 cw words + q + checks
+    uint8_t *d_ab = nullptr;
+    int32_t *d_status = nullptr;
+    float *h_rx = nullptr;          // pinned
+    uint64_t *h_out = nullptr;      // pinned: 16 cw words, q
+    uint8_t *h_ab = nullptr;
+    int32_t *h_status = nullptr;
+};
+
+struct DeviceCtx {
+    int device = -1;
+    int cus = 0;
+    std::mutex mu;
+    hipStream_t own_stream = nullptr;
+    std::map<void *, StreamRes> res;
+};
+
+std::mutex g_ctx_mu;
+std::map<int, std::unique_ptr<DeviceCtx>> g_ctx;
+
+int current_ctx(DeviceCtx **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    auto it = g_ctx.find(dev);
+    if (it == g_ctx.end()) {
+        auto c = std::make_unique<DeviceCtx>();
+        c->device = dev;
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        c->cus = prop.multiProcessorCount;
+        HIP_TRY(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+        it = g_ctx.emplace(dev, std::move(c)).first;
+    }
+    *out = it->second.get();
+    return GRAND_OK;
+}
+
+template <typename T>
+int ensure_device(T **p, size_t *cap, size_t want)
+{
+    if (*cap >= want && *p)
+        return GRAND_OK;
+    if (*p)
+        HIP_TRY(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    size_t n = std::max<size_t>(want, 64);
+    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess)
+        return fail(GRAND_ENOMEM, "hipMalloc failed for device buffer");
+    *cap = n;
+    return GRAND_OK;
+}
+
+template <typename T>
+int ensure_pinned(T **p, size_t *cap, size_t want)
+{
+    if (*cap >= want && *p)
+        return GRAND_OK;
+    if (*p)
+        HIP_TRY(hipHostFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    size_t n = std::max<size_t>(want, 64);
+    if (hipHostMalloc((void **)p, n * sizeof(T), hipHostMallocDefault) != hipSuccess)
+        return fail(GRAND_ENOMEM, "hipHostMalloc failed for staging buffer");
+    *cap = n;
+    return GRAND_OK;
+}
+
+int stream_res(DeviceCtx *ctx, void *stream, StreamRes **out)
+{
+    StreamRes &r = ctx->res[stream];
+    if (!r.queues) {
+        if (hipMalloc((void **)&r.queues, 64 * sizeof(uint32_t)) != hipSuccess)
+            return fail(GRAND_ENOMEM, "hipMalloc failed for work counters");
+        HIP_TRY(hipEventCreateWithFlags(&r.staged, hipEventDisableTiming));
+        if (hipMalloc((void **)&r.d_rx, 2 * kMaxItems * sizeof(float)) != hipSuccess ||
+            hipMalloc((void **)&r.d_out, (kCwStride + 2) * sizeof(uint64_t)) != hipSuccess ||
+            hipMalloc((void **)&r.d_ab, 64) != hipSuccess ||
+            hipMalloc((void **)&r.d_status, 64) != hipSuccess)
+            return fail(GRAND_ENOMEM, "hipMalloc failed for single-decode buffers");
+        if (hipHostMalloc((void **)&r.h_rx, 2 * kMaxItems * sizeof(float), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void **)&r.h_out, (kCwStride + 2) * sizeof(uint64_t),
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&r.h_ab, 64, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&r.h_status, 64, hipHostMallocDefault) != hipSuccess)
+            return fail(GRAND_ENOMEM, "hipHostMalloc failed for single-decode buffers");
+    }
+    *out = &r;
+    return GRAND_OK;
+}
+
+int ensure_scratch(StreamRes &r, size_t bytes)
+{
+    if (r.scratch_bytes >= bytes && r.scratch)
+        return GRAND_OK;
+    if (r.scratch) {
+        // scratch may still be in use by earlier launches on this stream
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(r.scratch));
+    }
+    r.scratch = nullptr;
+    r.scratch_bytes = 0;
+    if (hipMalloc((void **)&r.scratch, bytes) != hipSuccess)
+        return fail(GRAND_ENOMEM, "hipMalloc failed for decoder scratch (" +
+                                      std::to_string(bytes) + " bytes)");
+    r.scratch_bytes = bytes;
+    return GRAND_OK;
+}
+
+struct Bucket {
+    uint32_t n, M;
+    grand_tuning t;
+    std::vector<uint32_t> words;
+};
+
+// Enqueue one launch per bucket; jobs/codes already staged in device memory.
+int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buckets,
+                    const std::vector<uint32_t> &job_base, const float *rx, uint64_t *cw_out,
+                    uint64_t *q_out, uint8_t *ab_out, int32_t *status_out, uint64_t *checks_out,
+                    void *stream)
+{
+    size_t need = 0;
+    std::vector<uint32_t> grids(buckets.size());
+    for (size_t i = 0; i < buckets.size(); i++) {
+        const grand_tuning &t = buckets[i].t;
+        uint32_t g = std::min<uint32_t>((uint32_t)buckets[i].words.size(),
+                                        t.grid_per_cu * (uint32_t)ctx->cus);
+        grids[i] = std::max(1u, g);
+        SlotLayout L = slot_layout(t.node_cap, seg_cap_for(t), t.low_bits);
+        need = std::max<size_t>(need, (size_t)grids[i] * L.total);
+    }
+    int rc = ensure_scratch(r, need);
+    if (rc)
+        return rc;
+    for (size_t i = 0; i < buckets.size(); i++) {
+        const grand_tuning &t = buckets[i].t;
+        KernelArgs a;
+        a.codes = r.codes;
+        a.jobs = r.jobs + job_base[i];
+        a.njobs = (uint32_t)buckets[i].words.size();
+        a.low_bits = t.low_bits;
+        a.seg_len = t.seg_len;
+        a.first_band = t.first_band;
+        a.node_cap = t.node_cap;
+        a.seg_cap = seg_cap_for(t);
+        a.rx = rx;
+        a.cw_out = cw_out;
+        a.q_out = q_out;
+        a.ab_out = ab_out;
+        a.status_out = status_out;
+        a.checks_out = checks_out;
+        a.queue = r.queues + (i % 64);
+        a.scratch = r.scratch;
+        a.slot_bytes = slot_layout(t.node_cap, a.seg_cap, t.low_bits).total;
+        if (launch_reset(a.queue, stream))
+            return fail(GRAND_EDEVICE, "reset kernel launch failed");
+        if (launch_decode(a, grids[i], t.block, stream))
+            return fail(GRAND_EDEVICE, std::string("decode kernel launch failed: ") +
+                                           hipGetErrorString(hipGetLastError()));
+    }
+    return GRAND_OK;
+}
+
+}  // namespace
+
+// ==================================================================== ABI
+
+extern "C" {
+
+const char *grand_strerror(int err)
+{
+    switch (err) {
+    case GRAND_OK: return "success";
+    case GRAND_EINVAL: return "invalid argument";
+    case GRAND_ENOMEM: return "out of memory";
+    case GRAND_EDEVICE: return "HIP device error";
+    case GRAND_EBUSY: return "server busy (admission refused)";
+    case GRAND_ECAPACITY: return "decoder scratch capacity exceeded";
+    case GRAND_ENOTFOUND: return "not found";
+    default: return "unknown error";
+    }
+}
+
+const char *grand_last_error(void) { return g_last_error.c_str(); }
+
+int grand_init(int device)
+{
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(GRAND_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    DeviceCtx *ctx;
+    return current_ctx(&ctx);
+}
+
+int grand_code_create(uint32_t n, uint32_t rows, const uint64_t *h_rows, grand_code **out)
+{
+    if (!h_rows || !out)
+        return fail(GRAND_EINVAL, "null pointer");
+    if (n < 2 || n > kMaxN || (n & (n - 1)))
+        return fail(GRAND_EINVAL, "n must be a power of two in [2, 1024]");
+    if (rows < 1 || rows >= n || rows > 32 * kMaxKW)
+        return fail(GRAND_EINVAL, "rows must satisfy 1 <= rows < n and rows <= 512");
+    const uint32_t w64 = (n + 63) / 64;
+    for (uint32_t i = 0; i < rows; i++)
+        if (n % 64 && (h_rows[(size_t)i * w64 + w64 - 1] >> (n % 64)))
+            return fail(GRAND_EINVAL, "bits beyond n set in h_rows");
+    DeviceCtx *ctx;
+    int rc = current_ctx(&ctx);
+    if (rc)
+        return rc;
+    auto *c = new (std::nothrow) grand_code;
+    if (!c)
+        return fail(GRAND_ENOMEM, "host allocation failed");
+    c->n = n;
+    c->rows = rows;
+    c->kw = (rows + 31) / 32;
+    c->row_w32 = 2 * w64;
+    c->device = ctx->device;
+    std::vector<uint32_t> cols((size_t)n * c->kw, 0);
+    for (uint32_t i = 0; i < rows; i++)
+        for (uint32_t j = 0; j < n; j++)
+            if ((h_rows[(size_t)i * w64 + j / 64] >> (j % 64)) & 1ull)
+                cols[(size_t)j * c->kw + i / 32] |= 1u << (i % 32);
+    c->d_rows = nullptr;
+    c->d_cols = nullptr;
+    if (hipMalloc((void **)&c->d_rows, (size_t)rows * w64 * 8) != hipSuccess ||
+        hipMalloc((void **)&c->d_cols, cols.size() * 4) != hipSuccess) {
+        if (c->d_rows)
+            (void)hipFree(c->d_rows);
+        delete c;
+        return fail(GRAND_ENOMEM, "hipMalloc failed for code");
+    }
+    if (hipMemcpy(c->d_rows, h_rows, (size_t)rows * w64 * 8, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c->d_cols, cols.data(), cols.size() * 4, hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        (void)hipFree(c->d_rows);
+        (void)hipFree(c->d_cols);
+        delete c;
+        return fail(GRAND_EDEVICE, "copy of H to the device failed");
+    }
+    *out = c;
+    return GRAND_OK;
+}
+
+void grand_code_destroy(grand_code *code)
+{
+    if (!code)
+        return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(code->d_rows);
+    (void)hipFree(code->d_cols);
+    delete code;
+}
+
+uint32_t grand_code_n(const grand_code *code) { return code ? code->n : 0; }
+uint32_t grand_code_rows(const grand_code *code) { return code ? code->rows : 0; }
+
+int grand_tuning_get(uint32_t n, uint32_t M, grand_tuning *out)
+{
+    if (!out)
+        return fail(GRAND_EINVAL, "null pointer");
+    *out = tuning_for(n, M);
+    return GRAND_OK;
+}
+
+int grand_tuning_set(uint32_t n, uint32_t M, const grand_tuning *t)
+{
+    if (!t || !valid_tuning(*t))
+        return fail(GRAND_EINVAL, "invalid tuning");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[std::make_pair(n, M)] = *t;
+    return GRAND_OK;
+}
+
+int grand_decode(const grand_code *code, const float *rx, uint32_t M, float noise_var,
+                 uint64_t query_cap, uint64_t *codeword_out, uint64_t *queries_out,
+                 uint8_t *abandoned_out)
+{
+    if (!code || !rx || !codeword_out || !queries_out || !abandoned_out)
+        return fail(GRAND_EINVAL, "null pointer");
+    if (!valid_m(M))
+        return fail(GRAND_EINVAL, "M must be 4, 16, 64, 256, 1024 or 4096");
+    if (query_cap < 1 || query_cap > GRAND_MAX_CAP)
+        return fail(GRAND_EINVAL, "query cap out of range");
+    if (!std::isfinite(noise_var) || noise_var <= 0.0f)
+        return fail(GRAND_EINVAL, "noise variance must be finite and positive");
+    const uint32_t L = symbols(code->n, M);
+    for (uint32_t i = 0; i < 2 * L; i++)
+        if (!std::isfinite(rx[i]) || std::fabs(rx[i]) > 32768.0f)
+            return fail(GRAND_EINVAL, "received value not finite or beyond 2^15");
+    DeviceCtx *ctx;
+    int rc = current_ctx(&ctx);
+    if (rc)
+        return rc;
+    if (code->device != ctx->device)
+        return fail(GRAND_EINVAL, "code was created on another device");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    StreamRes *r;
+    rc = stream_res(ctx, (void *)ctx->own_stream, &r);   // private to this path
+    if (rc)
+        return rc;
+    hipStream_t st = ctx->own_stream;
+    if (r->staged_pending) {
+        HIP_TRY(hipEventSynchronize(r->staged));
+        r->staged_pending = false;
+    }
+    rc = ensure_device(&r->codes, &r->codes_cap, 1);
+    if (!rc)
+        rc = ensure_device(&r->jobs, &r->jobs_cap, 1);
+    if (!rc)
+        rc = ensure_pinned(&r->h_codes, &r->h_codes_cap, 1);
+    if (!rc)
+        rc = ensure_pinned(&r->h_jobs, &r->h_jobs_cap, 1);
+    if (rc)
+        return rc;
+    r->h_codes[0] = DevCode{code->n, code->rows, code->kw, code->row_w32, code->d_rows,
+                            code->d_cols};
+    r->h_jobs[0] = DevJob{0, M, 0, query_cap, 0, 0};
+    std::memcpy(r->h_rx, rx, 2 * L * sizeof(float));
+    HIP_TRY(hipMemcpyAsync(r->codes, r->h_codes, sizeof(DevCode), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r->jobs, r->h_jobs, sizeof(DevJob), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r->d_rx, r->h_rx, 2 * L * sizeof(float), hipMemcpyHostToDevice, st));
+    Bucket bk{code->n, M, tuning_for(code->n, M), {0}};
+    bk.t.grid_per_cu = 1;
+    std::vector<Bucket> buckets{bk};
+    std::vector<uint32_t> base{0};
+    rc = enqueue_buckets(ctx, *r, buckets, base, r->d_rx, r->d_out, r->d_out + kCwStride,
+                         r->d_ab, r->d_status, r->d_out + kCwStride + 1, st);
+    if (rc)
+        return rc;
+    HIP_TRY(hipMemcpyAsync(r->h_out, r->d_out, (kCwStride + 2) * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(r->h_ab, r->d_ab, 1, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(r->h_status, r->d_status, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (r->h_status[0] != GRAND_OK)
+        return fail(r->h_status[0], "device decode failed: " +
+                                        std::string(grand_strerror(r->h_status[0])));
+    const uint32_t w64 = (code->n + 63) / 64;
+    std::memcpy(codeword_out, r->h_out, w64 * sizeof(uint64_t));
+    *queries_out = r->h_out[kCwStride];
+    *abandoned_out = r->h_ab[0];
+    return GRAND_OK;
+}
+
+int grand_decode_batch(const grand_batch *b, void *stream)
+{
+    if (!b)
+        return fail(GRAND_EINVAL, "null batch");
+    if (b->count == 0)
+        return GRAND_OK;
+    if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
+        !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
+        return fail(GRAND_EINVAL, "null pointer in batch");
+    if (b->n_codes == 0)
+        return fail(GRAND_EINVAL, "no codes");
+    DeviceCtx *ctx;
+    int rc = current_ctx(&ctx);
+    if (rc)
+        return rc;
+    for (uint32_t c = 0; c < b->n_codes; c++)
+        if (!b->codes[c] || b->codes[c]->device != ctx->device)
+            return fail(GRAND_EINVAL, "null code or code on another device");
+    std::map<std::pair<uint32_t, uint32_t>, size_t> index;
+    std::vector<Bucket> buckets;
+    for (uint32_t i = 0; i < b->count; i++) {
+        uint32_t ci = b->code_index[i];
+        if (ci >= b->n_codes)
+            return fail(GRAND_EINVAL, "code index out of range");
+        if (!valid_m(b->M[i]))
+            return fail(GRAND_EINVAL, "invalid M");
+        if (b->query_cap[i] < 1 || b->query_cap[i] > GRAND_MAX_CAP)
+            return fail(GRAND_EINVAL, "query cap out of range");
+        if (!std::isfinite(b->noise_var[i]) || b->noise_var[i] <= 0.0f)
+            return fail(GRAND_EINVAL, "noise variance must be finite and positive");
+        auto key = std::make_pair(b->codes[ci]->n, b->M[i]);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            it = index.emplace(key, buckets.size()).first;
+            buckets.push_back(Bucket{key.first, key.second, tuning_for(key.first, key.second), {}});
+        }
+        buckets[it->second].words.push_back(i);
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    StreamRes *r;
+    rc = stream_res(ctx, stream, &r);
+    if (rc)
+        return rc;
+    if (r->staged_pending) {
+        HIP_TRY(hipEventSynchronize(r->staged));
+        r->staged_pending = false;
+    }
+    rc = ensure_device(&r->codes, &r->codes_cap, b->n_codes);
+    if (!rc)
+        rc = ensure_device(&r->jobs, &r->jobs_cap, b->count);
+    if (!rc)
+        rc = ensure_pinned(&r->h_codes, &r->h_codes_cap, b->n_codes);
+    if (!rc)
+        rc = ensure_pinned(&r->h_jobs, &r->h_jobs_cap, b->count);
+    if (rc)
+        return rc;
+    for (uint32_t c = 0; c < b->n_codes; c++) {
+        const grand_code *cd = b->codes[c];
+        r->h_codes[c] = DevCode{cd->n, cd->rows, cd->kw, cd->row_w32, cd->d_rows, cd->d_cols};
+    }
+    std::vector<uint32_t> job_base;
+    uint32_t k = 0;
+    for (auto &bk : buckets) {
+        job_base.push_back(k);
+        for (uint32_t i : bk.words)
+            r->h_jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i],
+                                    i, 0};
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(r->codes, r->h_codes, b->n_codes * sizeof(DevCode),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r->jobs, r->h_jobs, b->count * sizeof(DevJob), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipEventRecord(r->staged, st));
+    r->staged_pending = true;
+    return enqueue_buckets(ctx, *r, buckets, job_base, b->rx, b->codeword_out, b->queries_out,
+                           b->abandoned_out, b->status_out, b->checks_out, stream);
+}
+
+}  // extern "C"

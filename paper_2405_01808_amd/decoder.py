@@ -1,0 +1,145 @@
+"""Python binding of the GRAND decoder: argument marshalling over the C ABI.
+
+Every decoding step runs in the HIP library; torch provides device memory
+and streams only.  Conventions are those of include/grand.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _native as nat
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class Code:
+    """Decoder handle for a parity-check matrix H (rows x n, bit-packed rows).
+
+    h_rows: uint64 array of shape (rows, ceil(n/64)); bit j of row i is bit
+    j % 64 of h_rows[i, j // 64]."""
+
+    def __init__(self, n: int, h_rows):
+        h = np.ascontiguousarray(np.asarray(h_rows, dtype=np.uint64))
+        if h.ndim != 2 or h.shape[1] != (n + 63) // 64:
+            raise ValueError("h_rows must have shape (rows, ceil(n/64))")
+        self._lib = nat.lib()
+        handle = ctypes.c_void_p()
+        nat.check(self._lib.grand_code_create(n, h.shape[0], _ptr(h), ctypes.byref(handle)))
+        self.handle = handle
+        self.n = n
+        self.rows = h.shape[0]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.grand_code_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init(device: int = 0):
+    nat.check(nat.lib().grand_init(device))
+
+
+def decode(code: Code, rx, M: int, noise_var: float, cap: int):
+    """One decode with host buffers (synchronous).
+
+    Returns (codeword uint64[ceil(n/64)], queries, abandoned)."""
+    r = np.ascontiguousarray(np.asarray(rx, dtype=np.float32))
+    cw = np.zeros((code.n + 63) // 64, np.uint64)
+    q = ctypes.c_uint64(0)
+    ab = ctypes.c_uint8(0)
+    nat.check(nat.lib().grand_decode(code.handle, _ptr(r), int(M), float(noise_var), int(cap),
+                                     _ptr(cw), ctypes.byref(q), ctypes.byref(ab)))
+    return cw, q.value, ab.value
+
+
+@dataclass
+class BatchResult:
+    codewords: "object"   # torch.int64 [count, 16] (uint64 bit patterns)
+    queries: "object"     # torch.int64 [count]
+    abandoned: "object"   # torch.uint8 [count]
+    status: "object"      # torch.int32 [count]
+    checks: "object"      # torch.int64 [count]
+
+
+class BatchPlan:
+    """Host metadata and device outputs of a batch, reusable across calls."""
+
+    def __init__(self, codes, code_index, M, cap, noise_var, rx_offset, rx, device=None):
+        import torch
+        self.codes = list(codes)
+        self.count = len(code_index)
+        self.code_index = np.ascontiguousarray(code_index, dtype=np.uint32)
+        self.M = np.ascontiguousarray(M, dtype=np.uint32)
+        self.cap = np.ascontiguousarray(cap, dtype=np.uint64)
+        self.noise_var = np.ascontiguousarray(noise_var, dtype=np.float32)
+        self.rx_offset = np.ascontiguousarray(rx_offset, dtype=np.uint64)
+        if not (isinstance(rx, torch.Tensor) and rx.is_cuda and rx.dtype == torch.float32):
+            raise TypeError("rx must be a float32 CUDA (HIP) tensor")
+        self.rx = rx.contiguous()
+        dev = rx.device if device is None else device
+        n = self.count
+        self.out = BatchResult(
+            codewords=torch.zeros((max(n, 1), nat.CW_STRIDE), dtype=torch.int64, device=dev),
+            queries=torch.zeros(max(n, 1), dtype=torch.int64, device=dev),
+            abandoned=torch.zeros(max(n, 1), dtype=torch.uint8, device=dev),
+            status=torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
+            checks=torch.zeros(max(n, 1), dtype=torch.int64, device=dev))
+        self._handles = (ctypes.c_void_p * max(len(self.codes), 1))(
+            *[c.handle.value for c in self.codes])
+        b = nat.GrandBatch()
+        b.count = n
+        b.n_codes = len(self.codes)
+        b.codes = ctypes.cast(self._handles, ctypes.POINTER(ctypes.c_void_p))
+        b.code_index = _ptr(self.code_index)
+        b.M = _ptr(self.M)
+        b.query_cap = _ptr(self.cap)
+        b.noise_var = _ptr(self.noise_var)
+        b.rx_offset = _ptr(self.rx_offset)
+        b.rx = self.rx.data_ptr()
+        b.codeword_out = self.out.codewords.data_ptr()
+        b.queries_out = self.out.queries.data_ptr()
+        b.abandoned_out = self.out.abandoned.data_ptr()
+        b.status_out = self.out.status.data_ptr()
+        b.checks_out = self.out.checks.data_ptr()
+        self.desc = b
+
+    def launch(self, stream=None):
+        """Enqueue the whole batch on `stream` (default: torch's current stream)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.rx.device)
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        nat.check(nat.lib().grand_decode_batch(ctypes.byref(self.desc), ctypes.c_void_p(sp)))
+        return self.out
+
+
+def decode_batch(codes, code_index, M, cap, noise_var, rx_offset, rx, stream=None) -> BatchResult:
+    """Decode many codewords on the GPU (asynchronous on `stream`)."""
+    plan = BatchPlan(codes, code_index, M, cap, noise_var, rx_offset, rx)
+    out = plan.launch(stream)
+    out._plan = plan   # keep host metadata alive until the caller synchronises
+    return out
+
+
+def get_tuning(n: int, M: int) -> dict:
+    t = nat.GrandTuning()
+    nat.check(nat.lib().grand_tuning_get(n, M, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in nat.GrandTuning._fields_}
+
+
+def set_tuning(n: int, M: int, **kw):
+    cur = get_tuning(n, M)
+    cur.update(kw)
+    t = nat.GrandTuning(**cur)
+    nat.check(nat.lib().grand_tuning_set(n, M, ctypes.byref(t)))

@@ -1,0 +1,81 @@
+"""Shared helpers of the parity tests: run a list of workload Jobs through the
+oracle and through the HIP library, and compare element by element."""
+from __future__ import annotations
+
+import numpy as np
+
+import workload as w
+
+
+def h_rows(N, K):
+    return w.polar_code(N, K).h_rows
+
+
+def oracle_results(jobs, nthreads=None, cap=None):
+    import oracle
+    cws, q, ab, secs, used, wall = oracle.decode_jobs(jobs, h_rows, nthreads=nthreads, cap=cap)
+    return cws, q, ab
+
+
+class GpuCodes:
+    """One Code handle per (N, K), created on demand."""
+
+    def __init__(self):
+        self.codes = {}
+        self.order = []
+
+    def index(self, N, K):
+        import paper_2405_01808_amd as g
+        key = (N, K)
+        if key not in self.codes:
+            self.codes[key] = (len(self.order), g.Code(N, h_rows(N, K)))
+            self.order.append(self.codes[key][1])
+        return self.codes[key][0]
+
+
+def gpu_batch(jobs, codes: GpuCodes | None = None, cap=None, stream=None):
+    """Decode jobs in one grand_decode_batch call; returns numpy arrays
+    (codewords [count, 16] uint64, q uint64, abandoned uint8, status int32,
+    checks uint64)."""
+    import torch
+    import paper_2405_01808_amd as g
+    codes = codes or GpuCodes()
+    idx = np.array([codes.index(j.N, j.K) for j in jobs], np.uint32)
+    offs = np.zeros(len(jobs), np.uint64)
+    parts = []
+    o = 0
+    for i, j in enumerate(jobs):
+        offs[i] = o
+        parts.append(np.asarray(j.rx, np.float32))
+        o += len(j.rx)
+    rx = torch.from_numpy(np.concatenate(parts) if parts else np.zeros(1, np.float32)).cuda()
+    caps = np.array([j.cap if cap is None else cap for j in jobs], np.uint64)
+    nv = np.array([j.noise_var for j in jobs], np.float32)
+    Ms = np.array([j.M for j in jobs], np.uint32)
+    plan = g.BatchPlan(codes.order, idx, Ms, caps, nv, offs, rx)
+    out = plan.launch(stream)
+    torch.cuda.synchronize()
+    return (out.codewords.cpu().numpy().view(np.uint64), out.queries.cpu().numpy().view(np.uint64),
+            out.abandoned.cpu().numpy(), out.status.cpu().numpy(),
+            out.checks.cpu().numpy().view(np.uint64))
+
+
+def assert_parity(jobs, gpu, orc, indices=None, label=""):
+    """Bit-exact decoded word, query count and abandon flag."""
+    gcw, gq, gab, gst, gchk = gpu
+    ocw, oq, oab = orc
+    idxs = range(len(jobs)) if indices is None else indices
+    bad = []
+    for k, i in enumerate(idxs):
+        j = jobs[i] if indices is None else jobs[i]
+        nw = (j.N + 63) // 64
+        o_k = i if indices is None else k
+        ok = (gst[i] == 0 and int(gq[i]) == int(oq[o_k]) and int(gab[i]) == int(oab[o_k])
+              and np.array_equal(gcw[i, :nw], ocw[o_k]))
+        if not ok:
+            bad.append((i, j.N, j.M, int(gst[i]), int(gq[i]), int(oq[o_k]), int(gab[i]),
+                        int(oab[o_k])))
+    assert not bad, f"{label}: {len(bad)} mismatches, first: {bad[:5]}"
+    # performed checks are at least the query count
+    for i in idxs:
+        assert int(gchk[i]) >= int(gq[i]) or gab[i], (i, int(gchk[i]), int(gq[i]))

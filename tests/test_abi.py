@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/grand.h declares, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grand.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grand_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_matches_binding_list():
+    from paper_2405_01808_amd import _native as nat
+    assert declared_functions() == sorted(nat.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_01808_amd import _native as nat
+    assert os.path.exists(nat.LIB_PATH), "build libgrand.so first"
+    out = subprocess.run(["nm", "-D", "--defined-only", nat.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (grand_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    L = nat.lib()
+    for f in declared_functions():
+        assert hasattr(L, f)
+
+
+def test_strerror_covers_every_code():
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = L.grand_strerror(code).decode()
+        assert s and s != "unknown error"
+    assert L.grand_strerror(-99).decode() == "unknown error"
+
+
+def test_code_create_rejects_bad_arguments_on_host():
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    h = np.zeros((16, 1), np.uint64)
+    out = ctypes.c_void_p()
+    for n, rows in [(48, 16), (2048, 16), (1, 0), (32, 0), (32, 32), (1024, 513)]:
+        rc = L.grand_code_create(n, rows, h.ctypes.data, ctypes.byref(out))
+        assert rc == nat.GRAND_EINVAL, (n, rows)
+    assert L.grand_code_create(32, 16, None, ctypes.byref(out)) == nat.GRAND_EINVAL
+    hb = np.zeros((16, 1), np.uint64)
+    hb[3, 0] = 1 << 40                 # bit beyond n = 32
+    assert L.grand_code_create(32, 16, hb.ctypes.data, ctypes.byref(out)) == nat.GRAND_EINVAL
+    assert "beyond" in L.grand_last_error().decode()
+
+
+def test_decode_rejects_null_arguments_on_host():
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    rc = L.grand_decode(None, None, 4, 1.0, 10, None, None, None)
+    assert rc == nat.GRAND_EINVAL
+    b = nat.GrandBatch()
+    b.count = 3
+    assert L.grand_decode_batch(ctypes.byref(b), None) == nat.GRAND_EINVAL
+    assert L.grand_decode_batch(None, None) == nat.GRAND_EINVAL
+    b.count = 0
+    assert L.grand_decode_batch(ctypes.byref(b), None) == nat.GRAND_OK
+
+
+def test_tuning_table_roundtrip_and_validation():
+    import paper_2405_01808_amd as g
+    t = g.get_tuning(128, 16)
+    assert t["block"] % 64 == 0 and 0 <= t["low_bits"] <= 13
+    g.set_tuning(2, 4096, low_bits=3, block=64, seg_len=7)
+    assert g.get_tuning(2, 4096)["seg_len"] == 7
+    with pytest.raises(g.GrandError):
+        g.set_tuning(2, 4096, block=100)
+    with pytest.raises(g.GrandError):
+        g.set_tuning(2, 4096, low_bits=14)
+    with pytest.raises(g.GrandError):
+        g.set_tuning(2, 4096, seg_len=0)
