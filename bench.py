@@ -1,0 +1,158 @@
+"""Benchmark: GRAND decoding of Polar N=128 K=64, Gray 16-QAM, AWGN Eb/N0 ~
+U[3, 7] dB, 8192 codewords in one persistent launch, query cap 2^16.
+
+One step = one full decode of the batch (demap, ranking, Algorithm 1
+syndrome, ordered pattern checks, early exit or abandonment for every
+codeword).  Inputs are resident in device memory before timing starts.
+
+Prints one JSON line.  `value` is useful TEP syndrome checks per second: the
+sum over codewords of the query count q (the 1-based rank of the accepted
+pattern, or the cap on abandonment), divided by the timed wall time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "polar128_16qam"
+WORKLOAD_DESC = ("Polar N=128 K=64 (PW frozen set), Gray 16-QAM, AWGN Eb/N0 uniform in [3,7] dB, "
+                 "8192 codewords per step in one persistent launch, query cap 2^16")
+ALU_PEAK = 256 * 64 * 2.4e9          # 32-bit integer lane-ops/s (256 CU x 64 lanes x 2.4 GHz)
+OPS_PER_CHECK = 2                    # leading-word XOR + zero test per performed check
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(jobs, sample: int):
+    """The oracle on the host cores over the first `sample` codewords."""
+    import oracle
+    import workload as w
+    oracle.build(force=False)
+    sub = jobs[:sample]
+    nthreads = min(len(os.sched_getaffinity(0)), 64)
+    cws, q, ab, secs, used, wall = oracle.decode_jobs(
+        sub, lambda N, K: w.polar_code(N, K).h_rows, nthreads=nthreads)
+    return {"value": float(q.sum()) / wall, "unit": "TEP syndrome checks/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"first {len(sub)} of the {len(jobs)} codewords (same seeds), "
+                      f"{wall:.2f} s wall, {secs.sum():.1f} s of CPU work",
+            "codewords_per_s": len(sub) / wall,
+            "q": q, "ab": ab, "cws": cws}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--count", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this decoder runs on one GPU; --gpus must be 1 "
+                                   "(codewords are independent: see the sharding note)"}))
+        sys.exit(2)
+
+    import torch
+    import workload as w
+    import paper_2405_01808_amd as g
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    g.init(0)
+    t0 = time.time()
+    jobs = w.config_jobs(WORKLOAD, count=args.count)
+    log(f"generated {len(jobs)} codewords in {time.time() - t0:.1f}s")
+    code = g.Code(128, w.polar_code(128, 64).h_rows)
+    L2 = len(jobs[0].rx)
+    rx = torch.from_numpy(np.concatenate([j.rx for j in jobs])).to(dev)
+    offs = np.arange(len(jobs), dtype=np.uint64) * L2
+    plan = g.BatchPlan([code], np.zeros(len(jobs), np.uint32), [j.M for j in jobs],
+                       [j.cap for j in jobs], [j.noise_var for j in jobs], offs, rx)
+    stream = torch.cuda.current_stream(dev)
+
+    for i in range(args.warmup):
+        plan.launch(stream)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        out = plan.launch(stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_begin
+    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    log(f"timed {args.steps} steps: {wall:.3f}s wall, launch ms {launch_ms}")
+
+    q = out.queries.cpu().numpy().view(np.uint64)
+    ab = out.abandoned.cpu().numpy()
+    st = out.status.cpu().numpy()
+    checks = out.checks.cpu().numpy().view(np.uint64)
+    cws = out.codewords.cpu().numpy().view(np.uint64)
+    assert np.all(st == 0), f"device status errors: {np.unique(st)}"
+    sum_q = float(q.sum())
+    sum_checks = float(checks.sum())
+    ms_per_step = wall * 1e3 / args.steps
+    value = sum_q * args.steps / wall
+    bler = float(np.mean([not np.array_equal(w.unpack_bits(cws[i, :2], 128), jobs[i].cw)
+                          for i in range(len(jobs))]))
+    avg_launch_s = float(np.mean(launch_ms)) / 1e3
+    achieved = sum_checks * OPS_PER_CHECK / avg_launch_s
+
+    result = {
+        "metric": "TEP syndrome checks/s",
+        "value": value,
+        "unit": "checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_DESC, "codewords": len(jobs), "N": 128, "K": 64,
+                   "M": 16, "query_cap": 1 << 16},
+        "codewords_per_s": len(jobs) * args.steps / wall,
+        "performed_checks_per_s": sum_checks * args.steps / wall,
+        "mean_q": sum_q / len(jobs),
+        "abandon_rate": float(ab.mean()),
+        "bler": bler,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK,
+                     "unit": "int32 lane-ops/s", "frac": achieved / ALU_PEAK, "traffic": None,
+                     "kernel": "grand_decode_kernel",
+                     "work": f"{OPS_PER_CHECK} lane-ops x {int(sum_checks)} performed checks "
+                             f"per launch", "avg_launch_ms": avg_launch_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(jobs, min(args.cpu_sample, len(jobs)))
+        n = len(cb["q"])
+        mism = sum(int(q[i]) != int(cb["q"][i]) or int(ab[i]) != int(cb["ab"][i]) or
+                   not np.array_equal(cws[i, :2], cb["cws"][i]) for i in range(n))
+        result["parity_sample"] = {"codewords": n, "mismatches": int(mism)}
+        for k in ("q", "ab", "cws"):
+            cb.pop(k)
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -16,14 +16,15 @@
 //  3. Patterns (Steps 4-5): a pattern T splits into T_l, a subset of the b
 //     cheapest flips, and T_h, a subset of the others.  All 2^b low subsets
 //     are tabulated in LDS sorted by (cost, colex) with their syndromes; the
-//     high subsets ("nodes") with cost <= E are materialised in HBM with
+//     high subsets ("nodes") admitted so far are materialised in HBM with
 //     s(yhat) + sum of their columns.  Pattern (h, l) has syndrome
 //     S_h + LS_l, so its check is one K-bit comparison; the leading 32-bit
 //     word is compared first and the rest only on a match.
-//  4. Order and early exit: patterns are checked in cost bands
-//     (C_{t-1}, C_t].  For a fixed node the low entries of a band form one
-//     contiguous range of the sorted table, split into segments of <= S
-//     entries for the lanes.  The lowest (cost, colex) zero syndrome of the
+//  4. Order and early exit: patterns are checked in bands between
+//     thresholds that each admit a prefix of the (cost, colex) order (a
+//     whole cost level, or part of one when a level is too large).  For a
+//     fixed node the low entries of a band form one contiguous range of the
+//     sorted table, split into segments of <= S entries for the lanes.  The lowest (cost, colex) zero syndrome of the
 //     first band that has one is the answer; its 1-based rank q is counted
 //     exactly from the same sorted structures.  The search abandons when the
 //     bands cover the query cap.
@@ -60,7 +61,6 @@ struct Shared {
     uint32_t best_l;
     uint32_t overflow;
     int32_t cmax;
-    int32_t ct;
     unsigned long long acc;
 };
 
@@ -230,18 +230,55 @@ __device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t cnt, uint32
     return lo;
 }
 
-// Raise the node store from "all high subsets with cost <= E" to cost <= E'.
-// Children of a node add one rank above its largest; with costs ascending
-// the ranks giving a child cost in (E, E'] form one contiguous range.  When
-// the store would overflow the step is rolled back and E' halved.  Returns
-// the E' reached (E when even E + 1 does not fit; sh.overflow is then set).
-__device__ int32_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, uint32_t n,
-                                uint32_t node_cap, int32_t E, int32_t Ewant)
+// Search thresholds.  A threshold k = (C, R) admits a pattern T when
+// cost(T) < C, or cost(T) == C and maxrank(T) < R (maxrank of the empty set
+// is -1).  Because a smaller colex key never has a larger maximum, the
+// admitted set is always a prefix of the (cost, colex) order, so thresholds
+// may split one cost level -- needed when many patterns share one cost.
+// Thresholds are linearised as v = C * (n + 1) + R with 0 <= R <= n;
+// R = n admits the whole level.
+struct Thr {
+    int32_t C;
+    int32_t R;
+};
+
+__device__ inline Thr thr_of(int64_t v, uint32_t n)
+{
+    Thr t;
+    t.C = (int32_t)(v / (int64_t)(n + 1));
+    t.R = (int32_t)(v % (int64_t)(n + 1));
+    return t;
+}
+
+__device__ inline int64_t thr_full(int64_t C, uint32_t n) { return C * (int64_t)(n + 1) + n; }
+
+// Exclusive end of the child ranks r in [rl, n) whose child (cost cp + c_r,
+// maxrank r) threshold k admits.  Costs ascend with r, so the admitted
+// ranks are [rl, end).
+__device__ inline uint32_t child_end(const uint32_t *ikey, uint32_t rl, uint32_t n, Thr k,
+                                     int32_t cp)
+{
+    uint32_t A = ub_item(ikey, rl, n, (int64_t)k.C - 1 - cp);
+    uint32_t B = ub_item(ikey, A, n, (int64_t)k.C - cp);
+    uint32_t x = min(B, (uint32_t)max(k.R, 0));
+    return max(A, x);
+}
+
+// Raise the node store from "every high subset admitted by vE" to those
+// admitted by vwant.  Children of a node add one rank above its largest;
+// the admitted child ranks of a parent form one contiguous range.  When the
+// store would overflow, the step is rolled back and the threshold gap
+// halved.  Returns the threshold reached (vE when even vE + 1 does not fit;
+// sh.overflow is then set).
+__device__ int64_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, uint32_t n,
+                                uint32_t node_cap, int64_t vE, int64_t vwant)
 {
     const uint32_t tid = threadIdx.x, bs = blockDim.x, kw = code.kw;
     const uint32_t used0 = sh.used;
-    int32_t En = Ewant;
+    const Thr kE = thr_of(vE, n);
+    int64_t vn = vwant;
     for (;;) {
+        const Thr kn = thr_of(vn, n);
         bool ok = true;
         uint32_t pstart = 0, pend = used0;
         bool first = true;
@@ -252,10 +289,10 @@ __device__ int32_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, 
                 if (h < pend) {
                     int32_t ch = (int32_t)s.ncost[h];
                     uint32_t rl = (uint32_t)(s.nrank[h] + 1);
-                    if (ch <= En && rl < n) {
-                        lo = first ? ub_item(sh.ikey, rl, n, (int64_t)E - ch) : rl;
-                        uint32_t hi = ub_item(sh.ikey, lo, n, (int64_t)En - ch);
-                        cnt = hi - lo;
+                    if (rl < n) {
+                        lo = first ? child_end(sh.ikey, rl, n, kE, ch) : rl;
+                        uint32_t hi = child_end(sh.ikey, rl, n, kn, ch);
+                        cnt = hi > lo ? hi - lo : 0;
                     }
                 }
                 uint32_t total;
@@ -294,19 +331,46 @@ __device__ int32_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, 
             first = false;
         }
         if (ok)
-            return En;
+            return vn;
         __syncthreads();
         if (tid == 0)
             sh.used = used0;
         __syncthreads();
-        if (En - E <= 1) {
+        if (vn - vE <= 1) {
             if (tid == 0)
                 sh.overflow = 1;
             __syncthreads();
-            return E;
+            return vE;
         }
-        En = E + (En - E) / 2;
+        vn = vE + (vn - vE) / 2;
     }
+}
+
+// End of node h's admitted low-table entries under threshold k: entries with
+// cost_h + LC < C, plus the run with cost_h + LC == C when the pattern's
+// maxrank is below R (the node's own rank, or for the empty high subset the
+// highest bit of the low mask; within a run masks ascend).
+__device__ inline uint32_t node_end(const unsigned long long *lkey, uint32_t LB, Thr k,
+                                    int32_t ch, bool root, int32_t rank)
+{
+    uint32_t a = ub_low(lkey, 0, LB, (int64_t)k.C - 1 - ch);
+    uint32_t b = ub_low(lkey, a, LB, (int64_t)k.C - ch);
+    if (b == a)
+        return a;
+    if (!root)
+        return rank < k.R ? b : a;
+    if (k.R >= 16)
+        return b;
+    const unsigned long long lim = 1ull << k.R;   // masks below 2^R
+    uint32_t lo = a, hi = b;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if ((lkey[mid] & 0xFFFFull) < lim)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
 struct LaneHit {
@@ -490,7 +554,9 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
 
     // ---- cost bands -----------------------------------------------------
     const uint64_t cap = job.cap;
-    int32_t E = -1, cprev = -1;
+    const int64_t vmax = thr_full(cmax, n);   // admits every pattern
+    int64_t vE = 0;                           // the store holds the empty high subset
+    int64_t vprev = -1;
     uint64_t cum = 0, checks = 0;
     double histC[2] = {0, 0}, histN[2] = {0, 0};
     uint32_t band = 0;
@@ -502,36 +568,32 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
 
     for (;;) {
         // choose the band's threshold (uniform: every thread computes it)
-        int32_t ct;
+        const double cp = (double)thr_of(max<int64_t>(vprev, 0), n).C;
+        double cd;
         if (band == 0) {
             uint64_t k = min<uint64_t>(target, LB) - 1;
-            ct = (int32_t)(lkey[k] >> 16);
+            cd = (double)(lkey[k] >> 16);
         } else if (band == 1 || histN[0] <= 0.0) {
-            ct = 2 * cprev + 1;
+            cd = 2.0 * cp + 1.0;
         } else {
             double al = log(histN[1] / histN[0]) / log((histC[1] + 1.0) / (histC[0] + 1.0));
-            double want = (double)target;
-            double cd;
             if (!(al > 0.05) || !isfinite(al))
                 cd = 2.0 * histC[1] + 1.0;
             else
-                cd = (histC[1] + 1.0) * pow(want / histN[1], 1.0 / al) - 1.0;
-            if (!(cd < 2.0e9))
-                cd = 2.0e9;
-            ct = (int32_t)cd;
+                cd = (histC[1] + 1.0) * pow((double)target / histN[1], 1.0 / al) - 1.0;
         }
-        if (ct <= cprev)
-            ct = cprev + 1;
-        if (ct > cmax)
-            ct = cmax;
-        if (ct < cprev + 1)
-            ct = cprev + 1;   // only when cprev == cmax, handled below
-        if (ct > E)
-            ct = expand_nodes(sh, s, code, n, a.node_cap, E, ct);
-        E = max(E, ct);
-        if (ct <= cprev) {    // the store cannot grow any further
+        if (!(cd < 4.0e7))
+            cd = 4.0e7;
+        int64_t vt = thr_full((int64_t)cd, n);
+        vt = min(vt, vmax);
+        vt = max(vt, vprev + 1);
+        if (vt > vE) {
+            vt = expand_nodes(sh, s, code, n, a.node_cap, vE, vt);
+            vE = max(vE, vt);
+        }
+        if (vt <= vprev)      // the store cannot grow any further
             break;
-        }
+        const Thr kt = thr_of(vt, n);
 
         // segments of this band, checked as the list fills
         LaneHit best{0xFFFFFFFFu, kNone, 0};
@@ -545,9 +607,12 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
             if (h < used) {
                 int32_t ch = (int32_t)s.ncost[h];
                 lo = s.nptr[h];
-                if (ch <= ct && lo < LB) {
-                    hi = ub_low(lkey, lo, LB, (int64_t)ct - ch);
-                    cnt = (hi - lo + S - 1) / S;
+                if (lo < LB) {
+                    hi = node_end(lkey, LB, kt, ch, h == 0, s.nrank[h]);
+                    if (hi > lo)
+                        cnt = (hi - lo + S - 1) / S;
+                    else
+                        hi = lo;
                 }
             }
             band_size += hi > lo ? hi - lo : 0;
@@ -659,16 +724,16 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
             abandon = true;
             break;
         }
-        if (ct >= cmax) {          // every pattern has been checked
+        if (vt >= vmax) {          // every pattern has been checked
             q = cum;
             abandon = true;
             break;
         }
         histC[0] = histC[1];
         histN[0] = histN[1];
-        histC[1] = (double)ct;
+        histC[1] = (double)kt.C + (double)kt.R / (double)(n + 1);
         histN[1] = (double)cum;
-        cprev = ct;
+        vprev = vt;
         band++;
         uint64_t nt = cum * 4;
         target = min<uint64_t>(cap, nt);
