@@ -42,7 +42,7 @@ enum {
     GRAND_ENOMEM = -2,    /* host or device allocation failed */
     GRAND_EDEVICE = -3,   /* a HIP runtime call failed; see grand_last_error() */
     GRAND_EBUSY = -4,     /* server admission refused (memory budget or slot table full) */
-    GRAND_ECAPACITY = -5, /* a decode needed more device scratch than configured */
+    GRAND_ECAPACITY = -5, /* a decode needed more high-subset store than configured */
     GRAND_ENOTFOUND = -6  /* server: no such request, or nothing completed */
 };
 
@@ -141,11 +141,14 @@ int grand_decode_batch(const grand_batch *batch, void *stream);
 /* ------------------------------------------------------------------ */
 
 typedef struct {
-    uint32_t low_bits;     /* b: the b cheapest flips form the sorted low table (0..13) */
-    uint32_t block;        /* threads per workgroup (64..1024, multiple of 64) */
-    uint32_t seg_len;      /* low-table entries per check segment (1..256) */
-    uint32_t first_band;   /* patterns in the first cost band (>= 1) */
-    uint32_t node_cap;     /* high-pattern store per workgroup (entries) */
+    uint32_t low_bits;     /* b: the b cheapest flips form the sorted low table
+                              (0..13, and 2^b <= 8 * block) */
+    uint32_t block;        /* threads per workgroup (64..256, multiple of 64) */
+    uint32_t first_band;   /* patterns aimed at by the first cost band (>= 1) */
+    uint32_t band_growth;  /* each later band aims at growth x the patterns
+                              checked so far (2..64) */
+    uint32_t node_cap;     /* high-subset store entries per workgroup, held in
+                              device memory, 18 bytes each (64..2^22) */
     uint32_t grid_per_cu;  /* resident workgroups per compute unit for batches */
 } grand_tuning;
 

@@ -28,7 +28,7 @@ EXPORTS = [
 
 class GrandTuning(ctypes.Structure):
     _fields_ = [("low_bits", ctypes.c_uint32), ("block", ctypes.c_uint32),
-                ("seg_len", ctypes.c_uint32), ("first_band", ctypes.c_uint32),
+                ("first_band", ctypes.c_uint32), ("band_growth", ctypes.c_uint32),
                 ("node_cap", ctypes.c_uint32), ("grid_per_cu", ctypes.c_uint32)]
 
 

@@ -1,6 +1,6 @@
 // grand_api.hip -- host runtime behind include/grand.h: code handles, launch
-// planning (bucketing by (n, M) with per-bucket tuning), device scratch and
-// staging buffers, argument validation and error reporting.
+// planning (bucketing by (n, M) with per-bucket tuning), staging buffers,
+// argument validation and error reporting.
 
 #include <hip/hip_runtime.h>
 
@@ -73,12 +73,12 @@ grand_tuning builtin_tuning(uint32_t n, uint32_t M)
 {
     (void)M;
     grand_tuning t;
-    t.low_bits = n <= 64 ? 8 : 10;
+    t.low_bits = n <= 64 ? 8 : 9;
     t.block = 256;
-    t.seg_len = 32;
     t.first_band = 256;
+    t.band_growth = 4;
     t.node_cap = 1u << 16;
-    t.grid_per_cu = 2;
+    t.grid_per_cu = 6;
     return t;
 }
 
@@ -94,23 +94,24 @@ grand_tuning tuning_for(uint32_t n, uint32_t M)
     return builtin_tuning(n, M);
 }
 
+// LDS available to one workgroup on gfx950.
+constexpr uint32_t kLdsPerWorkgroup = 160u * 1024u;
+
 bool valid_tuning(const grand_tuning &t)
 {
-    return t.low_bits <= kMaxLowBits && t.block >= 64 && t.block <= kMaxBlock &&
-           t.block % 64 == 0 && t.seg_len >= 1 && t.seg_len <= 256 && t.first_band >= 1 &&
-           t.node_cap >= 64 && t.node_cap <= (1u << 22) && t.grid_per_cu >= 1 &&
-           t.grid_per_cu <= 32;
-}
-
-uint32_t seg_cap_for(const grand_tuning &t)
-{
-    uint32_t per = ((1u << t.low_bits) + t.seg_len - 1) / t.seg_len;
-    return t.block * per + t.block;
+    if (t.low_bits > kMaxLowBits || t.block < 64 || t.block > kMaxBlock || t.block % 64 ||
+        t.first_band < 1 || t.band_growth < 2 || t.band_growth > 64 || t.node_cap < 64 ||
+        t.node_cap > (1u << 22) || t.grid_per_cu < 1 || t.grid_per_cu > 32)
+        return false;
+    if ((1u << t.low_bits) > kMergePer * t.block)   // merge outputs per thread
+        return false;
+    // largest launch: 2L = 1024 flips
+    return 4ull * lds_layout(kMaxItems, t.block, t.low_bits).words + 256 <= kLdsPerWorkgroup;
 }
 
 // ---------------------------------------------------------------- device context
 struct StreamRes {
-    uint8_t *scratch = nullptr;
+    uint8_t *scratch = nullptr;     // high-subset stores, one slot per workgroup
     size_t scratch_bytes = 0;
     uint32_t *queues = nullptr;     // 64 counters
     DevJob *jobs = nullptr;
@@ -225,14 +226,14 @@ int ensure_scratch(StreamRes &r, size_t bytes)
     if (r.scratch_bytes >= bytes && r.scratch)
         return GRAND_OK;
     if (r.scratch) {
-        // scratch may still be in use by earlier launches on this stream
+        // earlier launches on any stream may still use the old buffer
         HIP_TRY(hipDeviceSynchronize());
         HIP_TRY(hipFree(r.scratch));
     }
     r.scratch = nullptr;
     r.scratch_bytes = 0;
     if (hipMalloc((void **)&r.scratch, bytes) != hipSuccess)
-        return fail(GRAND_ENOMEM, "hipMalloc failed for decoder scratch (" +
+        return fail(GRAND_ENOMEM, "hipMalloc failed for the high-subset stores (" +
                                       std::to_string(bytes) + " bytes)");
     r.scratch_bytes = bytes;
     return GRAND_OK;
@@ -250,15 +251,14 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
                     uint64_t *q_out, uint8_t *ab_out, int32_t *status_out, uint64_t *checks_out,
                     void *stream)
 {
-    size_t need = 0;
     std::vector<uint32_t> grids(buckets.size());
+    size_t need = 0;
     for (size_t i = 0; i < buckets.size(); i++) {
         const grand_tuning &t = buckets[i].t;
         uint32_t g = std::min<uint32_t>((uint32_t)buckets[i].words.size(),
                                         t.grid_per_cu * (uint32_t)ctx->cus);
         grids[i] = std::max(1u, g);
-        SlotLayout L = slot_layout(t.node_cap, seg_cap_for(t), t.low_bits);
-        need = std::max<size_t>(need, (size_t)grids[i] * L.total);
+        need = std::max<size_t>(need, (size_t)grids[i] * node_layout(t.node_cap).total);
     }
     int rc = ensure_scratch(r, need);
     if (rc)
@@ -270,10 +270,10 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
         a.jobs = r.jobs + job_base[i];
         a.njobs = (uint32_t)buckets[i].words.size();
         a.low_bits = t.low_bits;
-        a.seg_len = t.seg_len;
         a.first_band = t.first_band;
+        a.band_growth = t.band_growth;
         a.node_cap = t.node_cap;
-        a.seg_cap = seg_cap_for(t);
+        a.ni = items_pow2(buckets[i].n, buckets[i].M);
         a.rx = rx;
         a.cw_out = cw_out;
         a.q_out = q_out;
@@ -282,7 +282,6 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
         a.checks_out = checks_out;
         a.queue = r.queues + (i % 64);
         a.scratch = r.scratch;
-        a.slot_bytes = slot_layout(t.node_cap, a.seg_cap, t.low_bits).total;
         if (launch_reset(a.queue, stream))
             return fail(GRAND_EDEVICE, "reset kernel launch failed");
         if (launch_decode(a, grids[i], t.block, stream))
@@ -306,7 +305,7 @@ const char *grand_strerror(int err)
     case GRAND_ENOMEM: return "out of memory";
     case GRAND_EDEVICE: return "HIP device error";
     case GRAND_EBUSY: return "server busy (admission refused)";
-    case GRAND_ECAPACITY: return "decoder scratch capacity exceeded";
+    case GRAND_ECAPACITY: return "high-subset store capacity exceeded";
     case GRAND_ENOTFOUND: return "not found";
     default: return "unknown error";
     }

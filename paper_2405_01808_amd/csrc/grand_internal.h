@@ -11,7 +11,7 @@ constexpr uint32_t kMaxN = 1024;        // block length
 constexpr uint32_t kMaxItems = 1024;    // 2L <= N for M >= 4
 constexpr uint32_t kMaxKW = 16;         // syndrome words (rows <= 512)
 constexpr uint32_t kMaxLowBits = 13;    // low table <= 8192 entries
-constexpr uint32_t kMaxBlock = 1024;
+constexpr uint32_t kMaxBlock = 256;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kCwStride = 16;      // u64 words per codeword in batch outputs
 
@@ -39,11 +39,11 @@ struct KernelArgs {
     const DevCode *codes;
     const DevJob *jobs;
     uint32_t njobs;
-    uint32_t low_bits;    // b
-    uint32_t seg_len;     // S
-    uint32_t first_band;  // patterns in the first band
-    uint32_t node_cap;    // high-pattern store entries per workgroup
-    uint32_t seg_cap;     // segment list entries per workgroup
+    uint32_t low_bits;    // b: flips in the sorted low table
+    uint32_t first_band;  // patterns aimed at by the first band
+    uint32_t band_growth; // later bands aim at growth x the patterns checked so far
+    uint32_t node_cap;    // high-subset store entries per workgroup (HBM slot)
+    uint32_t ni;          // power of two >= 2L of every job of the launch
     const float *rx;
     uint64_t *cw_out;
     uint64_t *q_out;
@@ -51,35 +51,72 @@ struct KernelArgs {
     int32_t *status_out;  // may be null
     uint64_t *checks_out; // may be null
     uint32_t *queue;      // work counter, zero at launch
-    uint8_t *scratch;     // per-workgroup slots
-    uint64_t slot_bytes;
+    uint8_t *scratch;     // grid x node_layout(node_cap).total bytes
 };
 
-// Layout of one workgroup's scratch slot (byte offsets).
-struct SlotLayout {
-    uint64_t ncost, nparent, nrank, nptr, nsyn, seg, lsyn, total;
+// Layout of one workgroup's high-subset store (byte offsets; 18 B/entry).
+struct NodeLayout {
+    uint64_t cost, lead, par, rl, ptr, cnext, total;
 };
 
-__host__ __device__ inline SlotLayout slot_layout(uint32_t node_cap, uint32_t seg_cap, uint32_t low_bits)
+__host__ __device__ inline NodeLayout node_layout(uint32_t node_cap)
 {
-    SlotLayout s;
+    NodeLayout L;
     auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
     uint64_t o = 0;
-    s.ncost = o;   o = al(o + 4ull * node_cap);
-    s.nparent = o; o = al(o + 4ull * node_cap);
-    s.nrank = o;   o = al(o + 4ull * node_cap);
-    s.nptr = o;    o = al(o + 4ull * node_cap);
-    s.nsyn = o;    o = al(o + 4ull * kMaxKW * node_cap);
-    s.seg = o;     o = al(o + 8ull * seg_cap);
-    s.lsyn = o;    o = al(o + 4ull * kMaxKW * (1ull << low_bits));
-    s.total = o;
-    return s;
+    L.cost = o; o = al(o + 4ull * node_cap);
+    L.lead = o; o = al(o + 4ull * node_cap);
+    L.par = o;  o = al(o + 4ull * node_cap);
+    L.rl = o;   o = al(o + 2ull * node_cap);
+    L.ptr = o;  o = al(o + 2ull * node_cap);
+    L.cnext = o; o = al(o + 2ull * node_cap);
+    L.total = o;
+    return L;
 }
 
-// Dynamic LDS bytes for a low table of 2^b entries.
-inline uint32_t dyn_lds_bytes(uint32_t low_bits)
+constexpr uint32_t kMergePer = 8;    // low-table merge outputs per thread and level
+
+// Dynamic LDS of the decode kernel, in 32-bit words: the hard word and its
+// syndrome, the ranked flips and their columns' leading words (ni each),
+// the low flips' columns, scan partials, per-slot staging of a block of
+// nodes, and the low table (keys and leading syndrome words, 2^b each).
+struct LdsLayout {
+    uint32_t yhat, s0, ikey, col0, lcol, wsum, foff, fa, fb, fcost, flead, lkey, ls0, words;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uint32_t low_bits)
 {
-    return 12u << low_bits;   // u64 sort keys + u32 leading syndrome words
+    LdsLayout L;
+    uint32_t o = 0;
+    L.yhat = o;  o += kMaxN / 32;
+    L.s0 = o;    o += kMaxKW;
+    L.ikey = o;  o += ni;
+    L.col0 = o;  o += ni;
+    L.lcol = o;  o += kMaxLowBits * kMaxKW;
+    L.wsum = o;  o += kMaxBlock / 64;
+    L.foff = o;  o += block;
+    L.fa = o;    o += block;
+    L.fb = o;    o += block;
+    L.fcost = o; o += block;
+    L.flead = o; o += block;
+    o = (o + 1) & ~1u;          // 8-byte alignment of the table
+    L.lkey = o;  o += 1u << low_bits;
+    L.ls0 = o;   o += (1u << low_bits) + 8;   // padded for 8-wide reads
+    L.words = o;
+    return L;
+}
+
+// Power of two >= 2L for block length n and modulation order M.
+inline uint32_t items_pow2(uint32_t n, uint32_t M)
+{
+    uint32_t m = 0;
+    while ((1u << (2 * (m + 1))) <= M)
+        m++;
+    uint32_t two_l = 2 * ((n + 2 * m - 1) / (2 * m));
+    uint32_t p = 1;
+    while (p < two_l)
+        p <<= 1;
+    return p;
 }
 
 // Launch the decoder for one group of jobs sharing a tuning.

@@ -2,32 +2,38 @@
 // modulated polar codewords (arXiv 2405.01808, Section III, Algorithm 2).
 //
 // One workgroup decodes one codeword at a time and pulls codewords from a
-// work counter until the batch is drained (persistent launch).  Per codeword:
+// work counter until the batch is drained (persistent launch).  The sorted
+// flips, the low table and per-block staging live in LDS; the store of high
+// subsets lives in the workgroup's HBM slot and is read block by block with
+// coalesced loads.  Per codeword:
 //
 //  1. Demap (Algorithm 2 Step 1, Definitions 3.1 and 3.2): every (symbol,
 //     axis) is quantised to Q.12, sliced to the nearest odd amplitude, and
 //     yields the Gray bit whose flip moves to the near neighbour on the
 //     received value's side (reversed at the constellation edge) with cost
 //     d = 4096 - sigma * delta.  Flips are ranked by (cost, bit position)
-//     with a bitonic sort in LDS (Step 2).
+//     with a bitonic sort (Step 2).
 //  2. Hard-word syndrome s(yhat) = H yhat^T (Algorithm 1): AND of packed
 //     rows with yhat, parity per 32-bit word, then a wavefront ballot folds
 //     the words of a row -- the log2 N addition tree of pMult.
 //  3. Patterns (Steps 4-5): a pattern T splits into T_l, a subset of the b
-//     cheapest flips, and T_h, a subset of the others.  All 2^b low subsets
-//     are tabulated in LDS sorted by (cost, colex) with their syndromes; the
-//     high subsets ("nodes") admitted so far are materialised in HBM with
-//     s(yhat) + sum of their columns.  Pattern (h, l) has syndrome
-//     S_h + LS_l, so its check is one K-bit comparison; the leading 32-bit
-//     word is compared first and the rest only on a match.
+//     cheapest flips, and T_h, a subset of the others.  The 2^b low subsets
+//     are tabulated sorted by (cost, colex), built by b merge-path merges.
+//     The high subsets admitted so far ("nodes") form a forest: each node
+//     adds one rank above its parent's largest.  Pattern (h, l) has syndrome
+//     S_h + LS_l with S_h = s(yhat) + the node's columns, so checking it is
+//     one comparison.  Only the leading 32-bit syndrome word is kept per
+//     entry; the full K-bit comparison is rebuilt from the columns when the
+//     leading words match.
 //  4. Order and early exit: patterns are checked in bands between
 //     thresholds that each admit a prefix of the (cost, colex) order (a
 //     whole cost level, or part of one when a level is too large).  For a
-//     fixed node the low entries of a band form one contiguous range of the
-//     sorted table, split into segments of <= S entries for the lanes.  The lowest (cost, colex) zero syndrome of the
-//     first band that has one is the answer; its 1-based rank q is counted
-//     exactly from the same sorted structures.  The search abandons when the
-//     bands cover the query cap.
+//     fixed node the band's low entries form one contiguous range of the
+//     sorted table; the ranges of a block of nodes are laid end to end and
+//     cut into equal runs, one per thread.  The lowest (cost, colex) zero
+//     syndrome of the first band that has one is the answer; its 1-based
+//     rank q is counted exactly from the same sorted structures.  The search
+//     abandons when the bands cover the query cap.
 //
 // Everything is integer arithmetic except one exact float scaling per
 // received value; no packed-FP32 instructions are involved.
@@ -41,20 +47,12 @@ namespace grand {
 
 namespace {
 
+// Per-workgroup scalars (static LDS).
 struct Shared {
-    uint32_t yhat[kMaxN / 32];
-    uint32_t s0[kMaxKW];
-    uint32_t ikey[kMaxItems];        // sorted (cost << 10 | position)
-    uint32_t lcol[kMaxLowBits * kMaxKW];
-    uint32_t wsum[kMaxBlock / 64];
-    uint32_t foff[kMaxBlock];        // flat-expansion offsets
-    uint32_t fa[kMaxBlock];          // flat-expansion payload A
-    uint32_t fb[kMaxBlock];          // flat-expansion payload B
     uint32_t job;
     uint32_t nitems;
     uint32_t err;
     uint32_t used;                   // nodes in the store
-    uint32_t nseg;
     uint32_t hit_cost;
     uint32_t best_tid;
     uint32_t best_h;
@@ -62,6 +60,31 @@ struct Shared {
     uint32_t overflow;
     int32_t cmax;
     unsigned long long acc;
+};
+
+// Per-workgroup arrays in dynamic LDS, sized for the launch (lds_layout).
+struct Arr {
+    uint32_t *yhat;    // hard word, 32-bit words
+    uint32_t *s0;      // s(yhat)
+    uint32_t *ikey;    // sorted flips (cost << 10 | position)
+    uint32_t *col0;    // leading syndrome word of each rank's column
+    uint32_t *lcol;    // full columns of the low flips
+    uint32_t *wsum;    // scan partials, one per wave
+    uint32_t *foff;    // flat offsets of a block of nodes
+    uint32_t *fa;      // node of each slot
+    uint32_t *fb;      // first rank / low index of each slot
+    uint32_t *fcost;   // cost of each slot's node
+    uint32_t *flead;   // leading syndrome word of each slot's node
+};
+
+// Node store in the workgroup's HBM slot (structure of arrays).
+struct Nodes {
+    uint32_t *cost;    // cost of the high subset
+    uint32_t *lead;    // leading word of s(yhat) + its columns
+    uint32_t *par;     // parent (kNone for the empty subset, node 0)
+    uint16_t *rl;      // first child rank = own rank + 1 (b for node 0)
+    uint16_t *ptr;     // low-table entries already checked with this node
+    uint16_t *cnext;   // first child rank not yet in the store
 };
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -99,15 +122,14 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t *wsum, uint32_t *total)
 }
 
 // Bitonic sort of n (a power of two) keys in LDS, ascending.
-template <typename T>
-__device__ void bitonic_sort(T *a, uint32_t n)
+__device__ void bitonic_sort(uint32_t *a, uint32_t n)
 {
     for (uint32_t k = 2; k <= n; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
             for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
                 uint32_t ixj = i ^ j;
                 if (ixj > i) {
-                    T x = a[i], y = a[ixj];
+                    uint32_t x = a[i], y = a[ixj];
                     bool up = (i & k) == 0;
                     if ((x > y) == up) {
                         a[i] = y;
@@ -118,6 +140,33 @@ __device__ void bitonic_sort(T *a, uint32_t n)
             __syncthreads();
         }
     }
+}
+
+// Sort n <= 2 * blockDim distinct keys in LDS by counting, for each key,
+// the keys below it (one pass, all reads broadcast).  Pads (0xFFFFFFFF) are
+// first made distinct and stay above every real key.
+__device__ void rank_sort(uint32_t *a, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (a[i] == 0xFFFFFFFFu)
+            a[i] = 0xFFFF0000u | i;
+    __syncthreads();
+    uint32_t key[2] = {0, 0}, rank[2] = {0, 0};
+    for (uint32_t c = 0; c < 2; c++) {
+        uint32_t i = threadIdx.x + c * blockDim.x;
+        if (i < n) {
+            key[c] = a[i];
+            uint32_t r = 0;
+            for (uint32_t j = 0; j < n; j++)
+                r += a[j] < key[c];
+            rank[c] = r;
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = 0; c < 2; c++)
+        if (threadIdx.x + c * blockDim.x < n)
+            a[rank[c]] = key[c];
+    __syncthreads();
 }
 
 // First index in [lo, hi) whose item cost exceeds x (item costs ascending).
@@ -138,15 +187,18 @@ __device__ inline uint32_t ub_item(const uint32_t *ikey, uint32_t lo, uint32_t h
     return lo;
 }
 
+// Low-table keys: cost << 13 | mask (cost < 2^19 for b <= 13 flips).
+constexpr uint32_t kMaskBits = 13;
+constexpr uint32_t kMaskAll = (1u << kMaskBits) - 1;
+
 // First index in [lo, hi) of the sorted low table whose cost exceeds x.
-__device__ inline uint32_t ub_low(const unsigned long long *lkey, uint32_t lo, uint32_t hi,
-                                  int64_t x)
+__device__ inline uint32_t ub_low(const uint32_t *lkey, uint32_t lo, uint32_t hi, int64_t x)
 {
     if (x < 0)
         return lo;
-    if (x >= (1ll << 40))
+    if (x >= (1ll << 19))
         return hi;
-    unsigned long long key = ((unsigned long long)x << 16) | 0xFFFFull;
+    uint32_t key = ((uint32_t)x << kMaskBits) | kMaskAll;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
         if (lkey[mid] > key)
@@ -157,77 +209,55 @@ __device__ inline uint32_t ub_low(const unsigned long long *lkey, uint32_t lo, u
     return lo;
 }
 
-// Colex comparison of two high subsets given as nodes of the parent forest
-// (each node adds a rank larger than every rank of its parent, so walking to
-// the root lists the ranks in descending order).  Returns <0, 0, >0.
-__device__ int colex_cmp(const uint32_t *nparent, const int32_t *nrank, uint32_t a, uint32_t b)
+// Colex comparison of two high subsets given as nodes of the forest (each
+// node adds a rank larger than every rank of its parent, so walking to the
+// root lists the ranks in descending order).  Returns <0, 0, >0.
+__device__ int colex_cmp(const Nodes &nd, uint32_t a, uint32_t b)
 {
     for (;;) {
         if (a == b)
             return 0;
-        bool ea = nparent[a] == kNone, eb = nparent[b] == kNone;
-        if (ea && eb)
-            return 0;
-        if (ea)
+        if (a == 0)
             return -1;
-        if (eb)
+        if (b == 0)
             return 1;
-        int32_t ra = nrank[a], rb = nrank[b];
+        uint32_t ra = nd.rl[a], rb = nd.rl[b];
         if (ra != rb)
             return ra < rb ? -1 : 1;
-        a = nparent[a];
-        b = nparent[b];
+        a = nd.par[a];
+        b = nd.par[b];
     }
 }
 
 // (h1, l1) < (h2, l2) in colex order of the whole pattern, for equal costs.
-__device__ inline bool tep_less(const uint32_t *nparent, const int32_t *nrank,
-                                const unsigned long long *lkey, uint32_t h1, uint32_t l1,
+__device__ inline bool tep_less(const Nodes &nd, const uint32_t *lkey, uint32_t h1, uint32_t l1,
                                 uint32_t h2, uint32_t l2)
 {
-    int c = colex_cmp(nparent, nrank, h1, h2);
+    int c = colex_cmp(nd, h1, h2);
     if (c != 0)
         return c < 0;
-    return (lkey[l1] & 0xFFFFull) < (lkey[l2] & 0xFFFFull);
+    return (lkey[l1] & kMaskAll) < (lkey[l2] & kMaskAll);
 }
 
-struct Slot {
-    uint32_t *ncost;
-    uint32_t *nparent;
-    int32_t *nrank;
-    uint32_t *nptr;
-    uint32_t *nsyn;
-    unsigned long long *seg;
-    uint32_t *lsyn;
-};
-
-__device__ inline Slot slot_of(const KernelArgs &a)
+// Full K-bit syndrome test of pattern (h, l) whose leading words matched:
+// s(yhat) + columns of node h's ranks + columns of the low mask.
+__device__ bool full_zero(const Arr &A, const Nodes &nd, const DevCode &code,
+                          const uint32_t *lkey, uint32_t h, uint32_t l)
 {
-    SlotLayout L = slot_layout(a.node_cap, a.seg_cap, a.low_bits);
-    uint8_t *base = a.scratch + (uint64_t)blockIdx.x * a.slot_bytes;
-    Slot s;
-    s.ncost = (uint32_t *)(base + L.ncost);
-    s.nparent = (uint32_t *)(base + L.nparent);
-    s.nrank = (int32_t *)(base + L.nrank);
-    s.nptr = (uint32_t *)(base + L.nptr);
-    s.nsyn = (uint32_t *)(base + L.nsyn);
-    s.seg = (unsigned long long *)(base + L.seg);
-    s.lsyn = (uint32_t *)(base + L.lsyn);
-    return s;
-}
-
-// Find k in [0, cnt) with foff[k] <= j < foff[k + 1] (foff ascending).
-__device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t cnt, uint32_t j)
-{
-    uint32_t lo = 0, hi = cnt;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (foff[mid] <= j)
-            lo = mid;
-        else
-            hi = mid;
+    const uint32_t kw = code.kw;
+    const uint32_t mask = lkey[l] & kMaskAll;
+    for (uint32_t w = 1; w < kw; w++) {
+        uint32_t acc = A.s0[w];
+        for (uint32_t x = h; x != 0; x = nd.par[x]) {
+            uint32_t p = A.ikey[nd.rl[x] - 1] & 1023u;
+            acc ^= code.h_cols[(uint64_t)p * kw + w];
+        }
+        for (uint32_t m = mask; m; m &= m - 1)
+            acc ^= A.lcol[(__builtin_ctz(m)) * kw + w];
+        if (acc)
+            return false;
     }
-    return lo;
+    return true;
 }
 
 // Search thresholds.  A threshold k = (C, R) admits a pattern T when
@@ -264,16 +294,70 @@ __device__ inline uint32_t child_end(const uint32_t *ikey, uint32_t rl, uint32_t
     return max(A, x);
 }
 
-// Raise the node store from "every high subset admitted by vE" to those
-// admitted by vwant.  Children of a node add one rank above its largest;
-// the admitted child ranks of a parent form one contiguous range.  When the
-// store would overflow, the step is rolled back and the threshold gap
-// halved.  Returns the threshold reached (vE when even vE + 1 does not fit;
-// sh.overflow is then set).
-__device__ int64_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, uint32_t n,
-                                uint32_t node_cap, int64_t vE, int64_t vwant)
+// End of node h's admitted low-table entries under threshold k: entries with
+// cost_h + LC < C, plus the run with cost_h + LC == C when the pattern's
+// maxrank is below R (the node's own rank, or for the empty high subset the
+// highest bit of the low mask; within a run masks ascend).
+__device__ inline uint32_t node_end(const uint32_t *lkey, uint32_t LB, Thr k, int32_t ch,
+                                    uint32_t h, uint32_t rl, uint32_t ptr)
 {
-    const uint32_t tid = threadIdx.x, bs = blockDim.x, kw = code.kw;
+    // entries before ptr are already checked, and the end never moves back
+    if (ptr >= LB || (int64_t)ch + (lkey[ptr] >> kMaskBits) > (int64_t)k.C)
+        return ptr;
+    uint32_t a = ub_low(lkey, ptr, LB, (int64_t)k.C - 1 - ch);
+    uint32_t b = ub_low(lkey, a, LB, (int64_t)k.C - ch);
+    if (b == a)
+        return a;
+    if (h != 0)
+        return (int32_t)(rl - 1) < k.R ? b : a;
+    if (k.R >= (int32_t)kMaskBits)
+        return b;
+    const uint32_t lim = 1u << k.R;   // masks below 2^R
+    uint32_t lo = a, hi = b;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if ((lkey[mid] & kMaskAll) < lim)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Child rank r of a parent with cost cp is admitted by threshold k.
+__device__ inline bool child_admitted(const uint32_t *ikey, uint32_t r, Thr k, int32_t cp)
+{
+    int64_t c = (int64_t)cp + (ikey[r] >> 10);
+    return c < k.C || (c == k.C && (int32_t)r < k.R);
+}
+
+// Slot k of a block of nodes laid end to end: largest k in [lo, cnt) with
+// foff[k] <= j (foff ascending, foff[lo] <= j).
+__device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t lo, uint32_t cnt, uint32_t j)
+{
+    uint32_t hi = cnt;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (foff[mid] <= j)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Raise the node store from "every high subset admitted by vE" to those
+// admitted by vwant.  The admitted child ranks of a parent form one
+// contiguous range; children of old parents not admitted by vE are new, and
+// so are all admitted children of new parents.  When the store would
+// overflow, the step is rolled back and the threshold gap halved.  Returns
+// the threshold reached (vE when even vE + 1 does not fit; sh.overflow is
+// then set).
+__device__ int64_t expand_nodes(Shared &sh, const Arr &A, const Nodes &nd, uint32_t n,
+                                uint32_t node_cap,
+                                int64_t vE, int64_t vwant)
+{
+    const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const uint32_t used0 = sh.used;
     const Thr kE = thr_of(vE, n);
     int64_t vn = vwant;
@@ -285,41 +369,43 @@ __device__ int64_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, 
         while (ok && pstart < pend) {
             const uint32_t created_from = sh.used;
             for (uint32_t c0 = pstart; c0 < pend; c0 += bs) {
-                uint32_t h = c0 + tid, cnt = 0, lo = 0;
+                uint32_t h = c0 + tid, cnt = 0, lo = 0, ch = 0, lead = 0;
                 if (h < pend) {
-                    int32_t ch = (int32_t)s.ncost[h];
-                    uint32_t rl = (uint32_t)(s.nrank[h] + 1);
-                    if (rl < n) {
-                        lo = first ? child_end(sh.ikey, rl, n, kE, ch) : rl;
-                        uint32_t hi = child_end(sh.ikey, rl, n, kn, ch);
-                        cnt = hi > lo ? hi - lo : 0;
+                    ch = nd.cost[h];
+                    lo = first ? nd.cnext[h] : nd.rl[h];
+                    if (lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
+                        lead = nd.lead[h];
+                        uint32_t hi = child_end(A.ikey, lo, n, kn, (int32_t)ch);
+                        cnt = hi - lo;
                     }
                 }
                 uint32_t total;
-                uint32_t off = block_exscan(cnt, sh.wsum, &total);
+                uint32_t off = block_exscan(cnt, A.wsum, &total);
                 if (sh.used + total > node_cap) {
                     ok = false;   // uniform: every thread sees the same values
                     break;
                 }
-                sh.foff[tid] = off;
-                sh.fa[tid] = h;
-                sh.fb[tid] = lo;
+                A.foff[tid] = off;
+                A.fa[tid] = h;
+                A.fb[tid] = lo;
+                A.fcost[tid] = ch;
+                A.flead[tid] = lead;
+                if (h < pend && (cnt || !first))
+                    nd.cnext[h] = (uint16_t)(lo + cnt);
                 __syncthreads();
                 const uint32_t ncnt = min(bs, pend - c0);
                 const uint32_t dst0 = sh.used;
+                uint32_t k = 0;
                 for (uint32_t j = tid; j < total; j += bs) {
-                    uint32_t k = flat_owner(sh.foff, ncnt, j);
-                    uint32_t par = sh.fa[k];
-                    uint32_t r = sh.fb[k] + (j - sh.foff[k]);
+                    k = flat_owner(A.foff, k, ncnt, j);
+                    uint32_t r = A.fb[k] + (j - A.foff[k]);
                     uint32_t dst = dst0 + j;
-                    uint32_t key = sh.ikey[r];
-                    s.ncost[dst] = s.ncost[par] + (key >> 10);
-                    s.nparent[dst] = par;
-                    s.nrank[dst] = (int32_t)r;
-                    s.nptr[dst] = 0;
-                    const uint32_t *col = code.h_cols + (uint64_t)(key & 1023u) * kw;
-                    for (uint32_t w = 0; w < kw; w++)
-                        s.nsyn[(uint64_t)dst * kw + w] = s.nsyn[(uint64_t)par * kw + w] ^ col[w];
+                    nd.cost[dst] = A.fcost[k] + (A.ikey[r] >> 10);
+                    nd.lead[dst] = A.flead[k] ^ A.col0[r];
+                    nd.par[dst] = A.fa[k];
+                    nd.rl[dst] = (uint16_t)(r + 1);
+                    nd.ptr[dst] = 0;
+                    nd.cnext[dst] = (uint16_t)(r + 1);
                 }
                 __syncthreads();
                 if (tid == 0)
@@ -332,9 +418,12 @@ __device__ int64_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, 
         }
         if (ok)
             return vn;
+        // roll back: drop the new nodes and restore the old child frontiers
         __syncthreads();
         if (tid == 0)
             sh.used = used0;
+        for (uint32_t h = tid; h < used0; h += bs)
+            nd.cnext[h] = (uint16_t)child_end(A.ikey, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
         __syncthreads();
         if (vn - vE <= 1) {
             if (tid == 0)
@@ -346,77 +435,27 @@ __device__ int64_t expand_nodes(Shared &sh, const Slot &s, const DevCode &code, 
     }
 }
 
-// End of node h's admitted low-table entries under threshold k: entries with
-// cost_h + LC < C, plus the run with cost_h + LC == C when the pattern's
-// maxrank is below R (the node's own rank, or for the empty high subset the
-// highest bit of the low mask; within a run masks ascend).
-__device__ inline uint32_t node_end(const unsigned long long *lkey, uint32_t LB, Thr k,
-                                    int32_t ch, bool root, int32_t rank)
-{
-    uint32_t a = ub_low(lkey, 0, LB, (int64_t)k.C - 1 - ch);
-    uint32_t b = ub_low(lkey, a, LB, (int64_t)k.C - ch);
-    if (b == a)
-        return a;
-    if (!root)
-        return rank < k.R ? b : a;
-    if (k.R >= 16)
-        return b;
-    const unsigned long long lim = 1ull << k.R;   // masks below 2^R
-    uint32_t lo = a, hi = b;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((lkey[mid] & 0xFFFFull) < lim)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 struct LaneHit {
     uint32_t cost, h, l;
 };
 
-// Check every queued segment; keep each lane's lowest (cost, colex) hit.
-__device__ void check_segments(Shared &sh, const Slot &s, const unsigned long long *lkey,
-                               const uint32_t *ls0, uint32_t kw, LaneHit &best)
+__device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t *lkey,
+                                 uint32_t cost, uint32_t h, uint32_t l)
 {
-    const uint32_t nseg = sh.nseg;
-    for (uint32_t i = threadIdx.x; i < nseg; i += blockDim.x) {
-        unsigned long long sg = s.seg[i];
-        uint32_t h = (uint32_t)(sg >> 32);
-        uint32_t st = (uint32_t)(sg >> 16) & 0xFFFFu;
-        uint32_t ln = (uint32_t)sg & 0xFFFFu;
-        const uint32_t *sh_syn = s.nsyn + (uint64_t)h * kw;
-        uint32_t lead = sh_syn[0];
-        for (uint32_t l = st; l < st + ln; l++) {
-            if (ls0[l] == lead) {
-                bool eq = true;
-                for (uint32_t w = 1; w < kw; w++)
-                    eq = eq && (sh_syn[w] == s.lsyn[(uint64_t)l * kw + w]);
-                if (eq) {
-                    uint32_t cost = s.ncost[h] + (uint32_t)(lkey[l] >> 16);
-                    if (best.h == kNone || cost < best.cost ||
-                        (cost == best.cost &&
-                         tep_less(s.nparent, s.nrank, lkey, h, l, best.h, best.l))) {
-                        best.cost = cost;
-                        best.h = h;
-                        best.l = l;
-                    }
-                    break;   // later entries of this segment have larger keys
-                }
-            }
-        }
+    if (best.h == kNone || cost < best.cost ||
+        (cost == best.cost && tep_less(nd, lkey, h, l, best.h, best.l))) {
+        best.cost = cost;
+        best.h = h;
+        best.l = l;
     }
 }
 
-__device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *lkey,
-                           uint32_t *ls0, uint32_t jid)
+__device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
+                           uint32_t *ls0, const Nodes &nd, uint32_t jid)
 {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const DevJob job = a.jobs[jid];
     const DevCode code = a.codes[job.code];
-    const Slot s = slot_of(a);
     const uint32_t n_bits = code.n, kw = code.kw;
     uint32_t m = 0;
     while ((1u << (2 * (m + 1))) <= job.M && m < 6)
@@ -430,11 +469,11 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
 
     // ---- Step 1: demap ------------------------------------------------
     for (uint32_t i = tid; i < kMaxN / 32; i += bs)
-        sh.yhat[i] = 0;
+        A.yhat[i] = 0;
     for (uint32_t i = tid; i < kMaxKW; i += bs)
-        sh.s0[i] = 0;
+        A.s0[i] = 0;
     for (uint32_t i = tid; i < NI; i += bs)
-        sh.ikey[i] = 0xFFFFFFFFu;
+        A.ikey[i] = 0xFFFFFFFFu;
     if (tid == 0) {
         sh.nitems = 0;
         sh.err = 0;
@@ -451,15 +490,15 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
             continue;
         }
         int32_t xq = __float2int_rn(x * 4096.0f);     // exact scaling, ties to even
-        int32_t A = 2 * (xq >> 13) + 1;                // floor division by 8192
-        A = max(-(levels - 1), min(levels - 1, A));
-        int32_t delta = xq - A * 4096;
+        int32_t amp = 2 * (xq >> 13) + 1;                // floor division by 8192
+        amp = max(-(levels - 1), min(levels - 1, amp));
+        int32_t delta = xq - amp * 4096;
         int32_t sg = delta >= 0 ? 1 : -1;
-        if (A + 2 * sg > levels - 1 || A + 2 * sg < -(levels - 1))
+        if (amp + 2 * sg > levels - 1 || amp + 2 * sg < -(levels - 1))
             sg = -sg;                                  // reflect at the edge
         int32_t d = 4096 - sg * delta;
         uint32_t cost = (uint32_t)min(d, 32767);
-        uint32_t idx = (uint32_t)((A + levels - 1) >> 1);
+        uint32_t idx = (uint32_t)((amp + levels - 1) >> 1);
         uint32_t nbr = idx + (uint32_t)sg;
         uint32_t g = idx ^ (idx >> 1);
         uint32_t flip_bit = __builtin_ctz(max(idx, nbr));   // Gray(k-1)^Gray(k) = 2^ctz(k)
@@ -467,11 +506,11 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
         for (uint32_t k = 0; k < m; k++) {
             uint32_t p = base + k;
             if (p < n_bits && ((g >> (m - 1 - k)) & 1u))
-                atomicOr(&sh.yhat[p >> 5], 1u << (p & 31u));
+                atomicOr(&A.yhat[p >> 5], 1u << (p & 31u));
         }
         uint32_t p = base + (m - 1 - flip_bit);
         if (p < n_bits) {
-            sh.ikey[t] = (cost << 10) | p;
+            A.ikey[t] = (cost << 10) | p;
             atomicAdd(&sh.nitems, 1u);
             atomicAdd((uint32_t *)&sh.cmax, cost);
         }
@@ -484,9 +523,14 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
         return;
     }
     // ---- Step 2: rank the flips --------------------------------------
-    bitonic_sort(sh.ikey, NI);
+    if (NI <= 256 && NI <= 2 * bs)
+        rank_sort(A.ikey, NI);
+    else
+        bitonic_sort(A.ikey, NI);
     const uint32_t n = sh.nitems;
     const int32_t cmax = sh.cmax;
+    const uint32_t b = min(n, a.low_bits);
+    const uint32_t LB = 1u << b;
 
     // ---- Algorithm 1: s(yhat) = H yhat^T -----------------------------
     {
@@ -497,7 +541,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
             uint32_t bit = 0;
             if (t < total) {
                 uint32_t row = t / wn, w = t % wn;
-                bit = __popc(code.h_rows[(uint64_t)row * code.row_w32 + w] & sh.yhat[w]) & 1u;
+                bit = __popc(code.h_rows[(uint64_t)row * code.row_w32 + w] & A.yhat[w]) & 1u;
             }
             unsigned long long vote = __ballot(bit);
             if (t < total && (t % wn) == 0) {
@@ -506,152 +550,189 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
                 uint32_t parity = __popcll((vote >> first) & mask) & 1u;
                 uint32_t row = t / wn;
                 if (parity)
-                    atomicOr(&sh.s0[row >> 5], 1u << (row & 31u));
+                    atomicOr(&A.s0[row >> 5], 1u << (row & 31u));
             }
         }
     }
-    __syncthreads();
-
-    // ---- low table: all subsets of the b cheapest flips ---------------
-    const uint32_t b = min(n, a.low_bits);
-    const uint32_t LB = 1u << b;
+    // leading words of every rank's column, full columns of the low flips
+    for (uint32_t r = tid; r < n; r += bs)
+        A.col0[r] = code.h_cols[(uint64_t)(A.ikey[r] & 1023u) * kw];
     for (uint32_t i = tid; i < b * kw; i += bs) {
         uint32_t r = i / kw, w = i % kw;
-        sh.lcol[i] = code.h_cols[(uint64_t)(sh.ikey[r] & 1023u) * kw + w];
+        A.lcol[i] = code.h_cols[(uint64_t)(A.ikey[r] & 1023u) * kw + w];
     }
-    for (uint32_t e = tid; e < LB; e += bs) {
-        uint32_t cost = 0;
-        for (uint32_t r = 0; r < b; r++)
-            if ((e >> r) & 1u)
-                cost += sh.ikey[r] >> 10;
-        lkey[e] = ((unsigned long long)cost << 16) | e;
-    }
-    __syncthreads();
-    bitonic_sort(lkey, LB);
-    for (uint32_t i = tid; i < LB; i += bs) {
-        uint32_t mask = (uint32_t)(lkey[i] & 0xFFFFull);
-        uint32_t syn[kMaxKW];
-        for (uint32_t w = 0; w < kw; w++)
-            syn[w] = 0;
-        for (uint32_t r = 0; r < b; r++)
-            if ((mask >> r) & 1u)
-                for (uint32_t w = 0; w < kw; w++)
-                    syn[w] ^= sh.lcol[r * kw + w];
-        ls0[i] = syn[0];
-        for (uint32_t w = 0; w < kw; w++)
-            s.lsyn[(uint64_t)i * kw + w] = syn[w];
-    }
-    // root node: the empty high subset
-    if (tid == 0) {
-        s.ncost[0] = 0;
-        s.nparent[0] = kNone;
-        s.nrank[0] = (int32_t)b - 1;
-        s.nptr[0] = 0;
-    }
-    for (uint32_t w = tid; w < kw; w += bs)
-        s.nsyn[w] = sh.s0[w];
+    if (tid == 0)
+        lkey[0] = 0;
     __syncthreads();
 
-    // ---- cost bands -----------------------------------------------------
+    // ---- low table: merge A = subsets of flips < j with A + flip j -------
+    for (uint32_t j = 0; j < b; j++) {
+        const uint32_t len = 1u << j, outn = 2 * len;
+        const uint32_t add = ((A.ikey[j] >> 10) << kMaskBits) | (1u << j);
+        const uint32_t per = (outn + bs - 1) / bs;   // <= kMergePer (checked on the host)
+        const uint32_t i0 = min(outn, tid * per), i1 = min(outn, i0 + per);
+        uint32_t out[kMergePer];
+        if (i0 < i1) {
+            // co-rank: number of A entries among the first i0 outputs
+            uint32_t lo = i0 > len ? i0 - len : 0, hi = min(i0, len);
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (lkey[mid] < lkey[i0 - mid - 1] + add)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            uint32_t ia = lo, ib = i0 - lo;
+#pragma unroll
+            for (uint32_t k = 0; k < kMergePer; k++) {
+                if (k < i1 - i0) {
+                    bool takeA = ib >= len || (ia < len && lkey[ia] < lkey[ib] + add);
+                    out[k] = takeA ? lkey[ia] : lkey[ib] + add;
+                    ia += takeA;
+                    ib += !takeA;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < kMergePer; k++)
+            if (i0 + k < i1)
+                lkey[i0 + k] = out[k];
+        __syncthreads();
+    }
+    for (uint32_t i = tid; i < LB; i += bs) {
+        uint32_t acc = 0;
+        for (uint32_t msk = lkey[i] & kMaskAll; msk; msk &= msk - 1)
+            acc ^= A.col0[__builtin_ctz(msk)];
+        ls0[i] = acc;
+    }
+    // node 0: the empty high subset
+    if (tid == 0) {
+        nd.cost[0] = 0;
+        nd.lead[0] = A.s0[0];
+        nd.par[0] = kNone;
+        nd.rl[0] = (uint16_t)b;
+        nd.ptr[0] = 0;
+        nd.cnext[0] = (uint16_t)b;
+    }
+    __syncthreads();
+
+    // ---- bands ------------------------------------------------------------
     const uint64_t cap = job.cap;
     const int64_t vmax = thr_full(cmax, n);   // admits every pattern
     int64_t vE = 0;                           // the store holds the empty high subset
     int64_t vprev = -1;
     uint64_t cum = 0, checks = 0;
-    double histC[2] = {0, 0}, histN[2] = {0, 0};
+    float histC[2] = {0, 0}, histN[2] = {0, 0};
     uint32_t band = 0;
     bool found = false, abandon = false;
     uint64_t q = 0;
     uint32_t hit_h = kNone, hit_l = 0;
     uint64_t target = min<uint64_t>(cap, max<uint32_t>(a.first_band, 1u));
-    const uint32_t S = a.seg_len;
 
     for (;;) {
-        // choose the band's threshold (uniform: every thread computes it)
-        const double cp = (double)thr_of(max<int64_t>(vprev, 0), n).C;
-        double cd;
+        // the band's threshold (uniform: every thread computes the same).
+        // Only the amount of work per band depends on it, never the result:
+        // the count grows roughly like a power of the cost threshold, so
+        // the next threshold extrapolates the last two bands on a log scale.
+        const float cp = (float)thr_of(max<int64_t>(vprev, 0), n).C;
+        float cd;
         if (band == 0) {
-            uint64_t k = min<uint64_t>(target, LB) - 1;
-            cd = (double)(lkey[k] >> 16);
-        } else if (band == 1 || histN[0] <= 0.0) {
-            cd = 2.0 * cp + 1.0;
+            uint64_t k = min<uint64_t>(target, max(1u, LB / 4)) - 1;
+            cd = (float)(lkey[k] >> kMaskBits);
+        } else if (band == 1 || histN[0] <= 0.0f) {
+            cd = 2.0f * cp + 1.0f;
         } else {
-            double al = log(histN[1] / histN[0]) / log((histC[1] + 1.0) / (histC[0] + 1.0));
-            if (!(al > 0.05) || !isfinite(al))
-                cd = 2.0 * histC[1] + 1.0;
+            float al = __log2f(histN[1] / histN[0]) / __log2f((histC[1] + 1.0f) / (histC[0] + 1.0f));
+            if (!(al > 0.05f) || !isfinite(al))
+                cd = 2.0f * histC[1] + 1.0f;
             else
-                cd = (histC[1] + 1.0) * pow((double)target / histN[1], 1.0 / al) - 1.0;
+                cd = (histC[1] + 1.0f) * exp2f(__log2f((float)target / histN[1]) / al) - 1.0f;
         }
-        if (!(cd < 4.0e7))
-            cd = 4.0e7;
+        if (!(cd < 4.0e7f))
+            cd = 4.0e7f;
         int64_t vt = thr_full((int64_t)cd, n);
         vt = min(vt, vmax);
         vt = max(vt, vprev + 1);
         if (vt > vE) {
-            vt = expand_nodes(sh, s, code, n, a.node_cap, vE, vt);
+            vt = expand_nodes(sh, A, nd, n, a.node_cap, vE, vt);
             vE = max(vE, vt);
         }
         if (vt <= vprev)      // the store cannot grow any further
             break;
         const Thr kt = thr_of(vt, n);
 
-        // segments of this band, checked as the list fills
+        // checks: the band's ranges of a block of nodes end to end, one run
+        // of consecutive (node, entry) pairs per thread; each piece of a run
+        // that belongs to one node is a tight comparison loop
         LaneHit best{0xFFFFFFFFu, kNone, 0};
         uint64_t band_size = 0;
-        if (tid == 0)
-            sh.nseg = 0;
-        __syncthreads();
         const uint32_t used = sh.used;
         for (uint32_t c0 = 0; c0 < used; c0 += bs) {
-            uint32_t h = c0 + tid, cnt = 0, lo = 0, hi = 0;
+            uint32_t h = c0 + tid, cnt = 0, lo = 0, ch = 0, lead = 0;
             if (h < used) {
-                int32_t ch = (int32_t)s.ncost[h];
-                lo = s.nptr[h];
-                if (lo < LB) {
-                    hi = node_end(lkey, LB, kt, ch, h == 0, s.nrank[h]);
-                    if (hi > lo)
-                        cnt = (hi - lo + S - 1) / S;
-                    else
-                        hi = lo;
+                lo = nd.ptr[h];
+                ch = nd.cost[h];
+                lead = nd.lead[h];
+                uint32_t hi = node_end(lkey, LB, kt, (int32_t)ch, h, nd.rl[h], lo);
+                if (hi > lo) {
+                    cnt = hi - lo;
+                    nd.ptr[h] = (uint16_t)hi;
                 }
             }
-            band_size += hi > lo ? hi - lo : 0;
             uint32_t total;
-            uint32_t off = block_exscan(cnt, sh.wsum, &total);
-            if (sh.nseg + total > a.seg_cap) {
-                check_segments(sh, s, lkey, ls0, kw, best);
-                __syncthreads();
-                if (tid == 0)
-                    sh.nseg = 0;
-                __syncthreads();
-            }
-            const uint32_t base = sh.nseg;
-            for (uint32_t k = 0; k < cnt; k++) {
-                uint32_t st = lo + k * S;
-                uint32_t ln = min(S, hi - st);
-                s.seg[base + off + k] = ((unsigned long long)h << 32) |
-                                        ((unsigned long long)st << 16) | ln;
-            }
-            if (h < used && hi > lo)
-                s.nptr[h] = hi;
+            uint32_t off = block_exscan(cnt, A.wsum, &total);
+            A.foff[tid] = off;
+            A.fa[tid] = h;
+            A.fb[tid] = lo;
+            A.fcost[tid] = ch;
+            A.flead[tid] = lead;
             __syncthreads();
-            if (tid == 0)
-                sh.nseg = base + total;
+            band_size += total;
+            const uint32_t ncnt = min(bs, used - c0);
+            const uint32_t run = (total + bs - 1) / bs;
+            uint32_t j = tid * run;
+            const uint32_t jend = min(total, j + run);
+            if (j < jend) {
+                uint32_t k = flat_owner(A.foff, 0, ncnt, j);
+                while (j < jend) {
+                    const uint32_t kend = k + 1 < ncnt ? A.foff[k + 1] : total;
+                    const uint32_t e = min(jend, kend);
+                    const uint32_t l0 = A.fb[k] + (j - A.foff[k]);
+                    const uint32_t cntk = e - j;
+                    const uint32_t ld = A.flead[k];
+                    // min over (entry XOR lead) is zero iff a leading word
+                    // matches; reading up to 7 entries past the piece (the
+                    // table is padded) can only cause a spurious rescan below
+                    uint32_t mn = 0xFFFFFFFFu;
+                    for (uint32_t t = 0; t < cntk; t += 8) {
+                        const uint32_t *q8 = ls0 + l0 + t;
+                        mn = min(mn, min(min(q8[0] ^ ld, q8[1] ^ ld), min(q8[2] ^ ld, q8[3] ^ ld)));
+                        mn = min(mn, min(min(q8[4] ^ ld, q8[5] ^ ld), min(q8[6] ^ ld, q8[7] ^ ld)));
+                    }
+                    const bool any = mn == 0;
+                    if (any) {   // a leading word matched: verify and keep the best
+                        const uint32_t node = A.fa[k], nc = A.fcost[k];
+                        for (uint32_t t = 0; t < cntk; t++)
+                            if (ls0[l0 + t] == ld && full_zero(A, nd, code, lkey, node, l0 + t))
+                                keep_best(best, nd, lkey, nc + (lkey[l0 + t] >> kMaskBits), node,
+                                          l0 + t);
+                    }
+                    j = e;
+                    while (k + 1 < ncnt && A.foff[k + 1] <= j)
+                        k++;
+                }
+            }
             __syncthreads();
         }
-        check_segments(sh, s, lkey, ls0, kw, best);
 
-        // band size and best hit across the workgroup
-        if (tid == 0) {
-            sh.acc = 0;
+        // best hit of the band across the workgroup
+        if (tid == 0)
             sh.hit_cost = 0xFFFFFFFFu;
-        }
         __syncthreads();
-        atomicAdd(&sh.acc, (unsigned long long)band_size);
         if (best.h != kNone)
             atomicMin(&sh.hit_cost, best.cost);
         __syncthreads();
-        band_size = sh.acc;
         const uint32_t hc = sh.hit_cost;
         checks += band_size;
         cum += band_size;
@@ -675,7 +756,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
                     sh.best_tid = kNone;
                 __syncthreads();
                 if (cand && (best.h != bh || best.l != bl) &&
-                    tep_less(s.nparent, s.nrank, lkey, best.h, best.l, bh, bl))
+                    tep_less(nd, lkey, best.h, best.l, bh, bl))
                     atomicMin(&sh.best_tid, tid);
                 __syncthreads();
                 if (sh.best_tid == kNone)
@@ -694,14 +775,14 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
             __syncthreads();
             unsigned long long below = 0;
             for (uint32_t h = tid; h < used; h += bs) {
-                int32_t ch = (int32_t)s.ncost[h];
+                int32_t ch = (int32_t)nd.cost[h];
                 if (ch > (int32_t)hc)
                     continue;
                 uint32_t lo = ub_low(lkey, 0, LB, (int64_t)hc - 1 - ch);
                 uint32_t hi = ub_low(lkey, lo, LB, (int64_t)hc - ch);
                 below += lo;
                 if (hi > lo) {
-                    int c = colex_cmp(s.nparent, s.nrank, h, hit_h);
+                    int c = colex_cmp(nd, h, hit_h);
                     if (c < 0)
                         below += hi - lo;
                     else if (c == 0)
@@ -731,12 +812,11 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
         }
         histC[0] = histC[1];
         histN[0] = histN[1];
-        histC[1] = (double)kt.C + (double)kt.R / (double)(n + 1);
-        histN[1] = (double)cum;
+        histC[1] = (float)kt.C + (float)kt.R / (float)(n + 1);
+        histN[1] = (float)cum;
         vprev = vt;
         band++;
-        uint64_t nt = cum * 4;
-        target = min<uint64_t>(cap, nt);
+        target = min<uint64_t>(cap, cum * a.band_growth);
         __syncthreads();
     }
     __syncthreads();
@@ -748,22 +828,20 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
         for (uint32_t w = 0; w < kMaxN / 32; w++)
             flips[w] = 0;
         if (found) {
-            for (uint32_t h = hit_h; s.nparent[h] != kNone; h = s.nparent[h]) {
-                uint32_t p = sh.ikey[s.nrank[h]] & 1023u;
+            for (uint32_t h = hit_h; h != 0; h = nd.par[h]) {
+                uint32_t p = A.ikey[nd.rl[h] - 1] & 1023u;
                 flips[p >> 5] ^= 1u << (p & 31u);
             }
-            uint32_t mask = (uint32_t)(lkey[hit_l] & 0xFFFFull);
-            for (uint32_t r = 0; r < b; r++)
-                if ((mask >> r) & 1u) {
-                    uint32_t p = sh.ikey[r] & 1023u;
-                    flips[p >> 5] ^= 1u << (p & 31u);
-                }
+            for (uint32_t msk = lkey[hit_l] & kMaskAll; msk; msk &= msk - 1) {
+                uint32_t p = A.ikey[__builtin_ctz(msk)] & 1023u;
+                flips[p >> 5] ^= 1u << (p & 31u);
+            }
         }
         const uint32_t nw64 = (n_bits + 63) / 64;
         uint64_t *cw = a.cw_out + (uint64_t)out_slot * kCwStride;
         for (uint32_t w = 0; w < nw64; w++) {
-            uint64_t lo32 = sh.yhat[2 * w] ^ flips[2 * w];
-            uint64_t hi32 = (2 * w + 1 < kMaxN / 32) ? (sh.yhat[2 * w + 1] ^ flips[2 * w + 1]) : 0;
+            uint64_t lo32 = A.yhat[2 * w] ^ flips[2 * w];
+            uint64_t hi32 = A.yhat[2 * w + 1] ^ flips[2 * w + 1];
             uint64_t word = lo32 | (hi32 << 32);
             if (n_bits < 64)
                 word &= (1ull << n_bits) - 1;
@@ -772,18 +850,40 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, unsigned long long *
         a.q_out[out_slot] = q;
         a.ab_out[out_slot] = (uint8_t)(found ? 0 : 1);
         if (a.status_out)
-            a.status_out[out_slot] = capacity_fail || sh.overflow ? (capacity_fail ? -5 : 0) : 0;
+            a.status_out[out_slot] = capacity_fail ? -5 : 0;   // GRAND_ECAPACITY
         if (a.checks_out)
             a.checks_out[out_slot] = checks;
     }
 }
 
-__global__ __launch_bounds__(1024) void grand_decode_kernel(KernelArgs a)
+__global__ __launch_bounds__(256) void grand_decode_kernel(KernelArgs a)
 {
     __shared__ Shared sh;
-    extern __shared__ unsigned long long dyn[];
-    unsigned long long *lkey = dyn;
-    uint32_t *ls0 = (uint32_t *)(dyn + (1u << a.low_bits));
+    extern __shared__ uint32_t dyn[];
+    const LdsLayout ly = lds_layout(a.ni, blockDim.x, a.low_bits);
+    Arr A;
+    A.yhat = dyn + ly.yhat;
+    A.s0 = dyn + ly.s0;
+    A.ikey = dyn + ly.ikey;
+    A.col0 = dyn + ly.col0;
+    A.lcol = dyn + ly.lcol;
+    A.wsum = dyn + ly.wsum;
+    A.foff = dyn + ly.foff;
+    A.fa = dyn + ly.fa;
+    A.fb = dyn + ly.fb;
+    A.fcost = dyn + ly.fcost;
+    A.flead = dyn + ly.flead;
+    uint32_t *lkey = dyn + ly.lkey;
+    uint32_t *ls0 = dyn + ly.ls0;
+    const NodeLayout lay = node_layout(a.node_cap);
+    uint8_t *slot = a.scratch + (uint64_t)blockIdx.x * lay.total;
+    Nodes nd;
+    nd.cost = (uint32_t *)(slot + lay.cost);
+    nd.lead = (uint32_t *)(slot + lay.lead);
+    nd.par = (uint32_t *)(slot + lay.par);
+    nd.rl = (uint16_t *)(slot + lay.rl);
+    nd.ptr = (uint16_t *)(slot + lay.ptr);
+    nd.cnext = (uint16_t *)(slot + lay.cnext);
     for (;;) {
         if (threadIdx.x == 0)
             sh.job = atomicAdd(a.queue, 1u);
@@ -792,7 +892,7 @@ __global__ __launch_bounds__(1024) void grand_decode_kernel(KernelArgs a)
         __syncthreads();
         if (jid >= a.njobs)
             break;
-        decode_one(a, sh, lkey, ls0, jid);
+        decode_one(a, sh, A, lkey, ls0, nd, jid);
         __syncthreads();
     }
 }
@@ -807,8 +907,11 @@ __global__ void reset_kernel(uint32_t *q)
 
 int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stream)
 {
-    hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), dyn_lds_bytes(a.low_bits),
-                       (hipStream_t)stream, a);
+    const uint32_t lds = 4u * lds_layout(a.ni, block, a.low_bits).words;
+    if (hipFuncSetAttribute((const void *)grand_decode_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -3;
+    hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

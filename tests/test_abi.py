@@ -78,11 +78,17 @@ def test_tuning_table_roundtrip_and_validation():
     import paper_2405_01808_amd as g
     t = g.get_tuning(128, 16)
     assert t["block"] % 64 == 0 and 0 <= t["low_bits"] <= 13
-    g.set_tuning(2, 4096, low_bits=3, block=64, seg_len=7)
-    assert g.get_tuning(2, 4096)["seg_len"] == 7
+    g.set_tuning(2, 4096, low_bits=3, block=64, first_band=7)
+    assert g.get_tuning(2, 4096)["first_band"] == 7
     with pytest.raises(g.GrandError):
         g.set_tuning(2, 4096, block=100)
     with pytest.raises(g.GrandError):
         g.set_tuning(2, 4096, low_bits=14)
     with pytest.raises(g.GrandError):
-        g.set_tuning(2, 4096, seg_len=0)
+        g.set_tuning(2, 4096, first_band=0)
+    with pytest.raises(g.GrandError):
+        g.set_tuning(2, 4096, node_cap=(1 << 22) + 1)
+    with pytest.raises(g.GrandError):              # 2^b above 8 merge outputs per thread
+        g.set_tuning(2, 4096, block=64, low_bits=10)
+    with pytest.raises(g.GrandError):
+        g.set_tuning(2, 4096, block=512)

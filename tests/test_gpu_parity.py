@@ -70,11 +70,11 @@ def test_uneven_mix_batch(gpu):
     assert_parity(jobs, g, o, label="uneven mix")
 
 
-@pytest.mark.parametrize("tuning", [dict(low_bits=0), dict(low_bits=1, seg_len=1),
-                                    dict(low_bits=4, block=64, seg_len=3),
-                                    dict(low_bits=13, block=1024, seg_len=256),
+@pytest.mark.parametrize("tuning", [dict(low_bits=0), dict(low_bits=1, band_growth=2),
+                                    dict(low_bits=4, block=64, band_growth=64),
+                                    dict(low_bits=11, block=256, node_cap=4096),
                                     dict(low_bits=6, first_band=1, node_cap=64),
-                                    dict(low_bits=11, block=128, first_band=100000)])
+                                    dict(low_bits=10, block=128, first_band=100000)])
 def test_results_do_not_depend_on_tuning(gpu, tuning):
     """Every tuning must give the same exact answer."""
     jobs = w.jobs_from_spec("tune", seed=11, count=40, cap=4000, Ns=(64,), Ms=(16,),
