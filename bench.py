@@ -51,6 +51,55 @@ def cpu_baseline(jobs, sample: int):
             "q": q, "ab": ab, "cws": cws}
 
 
+def serving(g, w, count: int, plain_count: int):
+    """Poisson replay of the serving mix (2e5 requests/s) through the server
+    and through one grand_decode per request."""
+    jobs = w.config_jobs("serving_mix", count=count)
+    codes, order, idx = {}, [], []
+    for j in jobs:
+        if (j.N, j.K) not in codes:
+            codes[(j.N, j.K)] = len(order)
+            order.append(g.Code(j.N, w.polar_code(j.N, j.K).h_rows))
+        idx.append(codes[(j.N, j.K)])
+    arrivals = np.array([j.arrival_s for j in jobs]) - jobs[0].arrival_s
+    trace = g.Trace(order, idx, [j.M for j in jobs], [j.cap for j in jobs],
+                    [j.noise_var for j in jobs], [j.rx for j in jobs], arrivals)
+    srv = g.Server(max_inflight=16384, lanes=8, max_batch=2048, memory_budget=48 << 30)
+    res, wall = trace.run_server(srv)
+    assert all(r.status == 0 for r in res), "server request errors"
+    lat = np.array([r.latency_s for r in res]) * 1e3
+    groups = {}
+    for j, l in zip(jobs, lat):
+        groups.setdefault((j.N, j.M), []).append(l)
+    for k in sorted(groups, key=lambda k: -np.percentile(groups[k], 99))[:6]:
+        log(f"serving (N, M)={k}: n={len(groups[k])} p50 {np.percentile(groups[k], 50):.3f} ms "
+            f"p99 {np.percentile(groups[k], 99):.3f} ms")
+    q = np.array([r.queries for r in res], dtype=np.float64)
+    out = {"requests": len(jobs), "arrival_rate": 2e5, "wall_s": wall,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "codewords_per_s": len(jobs) / wall, "checks_per_s": float(q.sum()) / wall,
+           "abandon_rate": float(np.mean([r.abandoned for r in res]))}
+    srv.close()
+    if plain_count:
+        sub = jobs[:plain_count]
+        ptrace = g.Trace(order, idx[:plain_count], [j.M for j in sub], [j.cap for j in sub],
+                         [j.noise_var for j in sub], [j.rx for j in sub],
+                         arrivals[:plain_count])
+        pres, pwall = ptrace.run_plain()
+        plat = np.array([r.latency_s for r in pres]) * 1e3
+        pq = np.array([r.queries for r in pres], dtype=np.float64)
+        out["plain"] = {"requests": plain_count, "wall_s": pwall,
+                        "p50_ms": float(np.percentile(plat, 50)),
+                        "p99_ms": float(np.percentile(plat, 99)),
+                        "codewords_per_s": plain_count / pwall,
+                        "checks_per_s": float(pq.sum()) / pwall}
+        same = all(r.queries == p.queries and r.abandoned == p.abandoned and
+                   np.array_equal(r.codeword[:(j.N + 63) // 64], p.codeword[:(j.N + 63) // 64])
+                   for r, p, j in zip(res, pres, sub))
+        out["plain"]["identical_results"] = bool(same)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +108,8 @@ def main():
     ap.add_argument("--count", type=int, default=8192)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=20000)
+    ap.add_argument("--plain-count", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this decoder runs on one GPU; --gpus must be 1 "
@@ -142,6 +193,10 @@ def main():
                      "work": f"{OPS_PER_CHECK} lane-ops x {int(sum_checks)} performed checks "
                              f"per launch", "avg_launch_ms": avg_launch_s * 1e3},
     }
+    if args.serve_count:
+        t0 = time.time()
+        result["serving"] = serving(g, w, args.serve_count, args.plain_count)
+        log(f"serving replay done in {time.time() - t0:.1f}s")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(jobs, min(args.cpu_sample, len(jobs)))
         n = len(cb["q"])

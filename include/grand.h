@@ -158,6 +158,99 @@ typedef struct {
 int grand_tuning_get(uint32_t n, uint32_t M, grand_tuning *out);
 int grand_tuning_set(uint32_t n, uint32_t M, const grand_tuning *t);
 
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuously batched decoding of a request stream          */
+/* ------------------------------------------------------------------ */
+
+/* A server admits requests (Algorithm 2 decodes, one codeword each) as they
+ * arrive, within a slot count and a device-memory budget, and keeps several
+ * HIP streams ("lanes") busy: whenever a lane is free, every admitted request
+ * not yet on the device is staged and launched on it as one batch, so
+ * batches launched at different times overlap on the device while new
+ * requests keep being admitted.  A request's result is bit-identical to
+ * grand_decode of the same input, whatever else is in flight.  Server calls
+ * are serialised internally and may come from several host threads. */
+typedef struct grand_server grand_server;
+
+typedef struct {
+    uint32_t max_inflight;     /* admitted, not yet returned requests (1..2^20) */
+    uint32_t lanes;            /* streams used concurrently (1..8) */
+    uint32_t max_batch;        /* requests per launch (1..65536) */
+    uint32_t pad;
+    uint64_t memory_budget;    /* device bytes reserved for admitted requests;
+                                  each reserves grand_request_bytes(n, M) */
+} grand_server_config;
+
+typedef struct {
+    uint64_t request_id;
+    uint64_t codeword[16];     /* ceil(n/64) words used */
+    uint64_t queries;
+    uint64_t checks;           /* syndrome checks performed (>= queries unless abandoned) */
+    int32_t status;            /* GRAND_OK or a per-request error (GRAND_ECAPACITY) */
+    uint8_t abandoned;
+    uint8_t pad[3];
+    double arrival_s;          /* trace replays: scheduled arrival; otherwise = submit_s */
+    double submit_s;           /* host steady-clock seconds when admitted */
+    double complete_s;         /* host steady-clock seconds when completion was observed */
+} grand_result;
+
+/* Device bytes one request of length n and modulation M reserves while
+ * admitted (its received values, outputs and one high-subset store). */
+uint64_t grand_request_bytes(uint32_t n, uint32_t M);
+
+int grand_server_create(const grand_server_config *cfg, grand_server **out);
+/* Waits for work on the device, then releases everything. */
+void grand_server_destroy(grand_server *server);
+
+/* Admit one request; rx (2L floats, host) is copied.  Returns GRAND_EBUSY,
+ * leaving no state, when the slot count or the memory budget would be
+ * exceeded; GRAND_EINVAL for bad arguments (as grand_decode). */
+int grand_server_submit(grand_server *server, const grand_code *code, const float *rx,
+                        uint32_t M, float noise_var, uint64_t query_cap,
+                        uint64_t *request_id);
+
+/* Withdraw an admitted request that has not been launched yet
+ * (GRAND_ENOTFOUND otherwise); its slot and memory are released. */
+int grand_server_cancel(grand_server *server, uint64_t request_id);
+
+/* Launch admitted requests on free lanes and collect finished ones, without
+ * blocking: up to max_out results are written to out (host) and their count
+ * to *n_out. */
+int grand_server_poll(grand_server *server, grand_result *out, uint32_t max_out,
+                      uint32_t *n_out);
+
+/* Requests admitted but not launched, on the device, and bytes reserved. */
+int grand_server_stats(grand_server *server, uint64_t *pending, uint64_t *running,
+                       uint64_t *memory_in_use);
+
+/* One request of a recorded arrival stream. */
+typedef struct {
+    uint32_t code_index;       /* into codes[] */
+    uint32_t M;
+    uint64_t query_cap;
+    uint64_t rx_offset;        /* float offset into rx (host) */
+    float noise_var;
+    float pad;
+    double arrival_s;          /* seconds after the start of the replay, ascending */
+} grand_trace_req;
+
+/* Replay an arrival stream in real time through the server: each request is
+ * submitted at its arrival time (later if admission refuses), and the host
+ * polls until every request has completed.  results[i] belongs to reqs[i];
+ * its latency is complete_s - arrival_s.  *wall_s receives the replay's
+ * duration. */
+int grand_server_run_trace(grand_server *server, const grand_code *const *codes,
+                           uint32_t n_codes, const grand_trace_req *reqs, uint32_t count,
+                           const float *rx, grand_result *results, double *wall_s);
+
+/* The same stream decoded one request per grand_decode call (one launch and
+ * one synchronisation per request), in arrival order: the baseline the
+ * server is compared with. */
+int grand_plain_run_trace(const grand_code *const *codes, uint32_t n_codes,
+                          const grand_trace_req *reqs, uint32_t count, const float *rx,
+                          grand_result *results, double *wall_s);
+
 #ifdef __cplusplus
 }
 #endif

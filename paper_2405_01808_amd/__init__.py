@@ -4,3 +4,4 @@ package only marshals arguments to its C ABI (include/grand.h)."""
 from .decoder import (Code, BatchPlan, BatchResult, decode, decode_batch, get_tuning,  # noqa: F401
                       init, set_tuning)
 from ._native import GrandError, CW_STRIDE, GRAND_MAX_CAP  # noqa: F401
+from .server import Server, Trace, Result, request_bytes  # noqa: F401

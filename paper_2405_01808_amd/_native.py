@@ -23,6 +23,9 @@ EXPORTS = [
     "grand_strerror", "grand_last_error", "grand_init",
     "grand_code_create", "grand_code_destroy", "grand_code_n", "grand_code_rows",
     "grand_decode", "grand_decode_batch", "grand_tuning_get", "grand_tuning_set",
+    "grand_request_bytes", "grand_server_create", "grand_server_destroy", "grand_server_submit",
+    "grand_server_cancel", "grand_server_poll", "grand_server_stats", "grand_server_run_trace",
+    "grand_plain_run_trace",
 ]
 
 
@@ -41,6 +44,27 @@ class GrandBatch(ctypes.Structure):
                 ("codeword_out", ctypes.c_void_p), ("queries_out", ctypes.c_void_p),
                 ("abandoned_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
                 ("checks_out", ctypes.c_void_p)]
+
+
+class GrandServerConfig(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("memory_budget", ctypes.c_uint64)]
+
+
+class GrandResult(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("codeword", ctypes.c_uint64 * 16),
+                ("queries", ctypes.c_uint64), ("checks", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("abandoned", ctypes.c_uint8),
+                ("pad", ctypes.c_uint8 * 3), ("arrival_s", ctypes.c_double),
+                ("submit_s", ctypes.c_double), ("complete_s", ctypes.c_double)]
+
+
+class GrandTraceReq(ctypes.Structure):
+    _fields_ = [("code_index", ctypes.c_uint32), ("M", ctypes.c_uint32),
+                ("query_cap", ctypes.c_uint64), ("rx_offset", ctypes.c_uint64),
+                ("noise_var", ctypes.c_float), ("pad", ctypes.c_float),
+                ("arrival_s", ctypes.c_double)]
 
 
 class GrandError(RuntimeError):
@@ -84,6 +108,30 @@ def lib():
     L.grand_tuning_get.restype = i32
     L.grand_tuning_set.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]
     L.grand_tuning_set.restype = i32
+    L.grand_request_bytes.argtypes = [u32, u32]
+    L.grand_request_bytes.restype = u64
+    L.grand_server_create.argtypes = [ctypes.POINTER(GrandServerConfig), ctypes.POINTER(vp)]
+    L.grand_server_create.restype = i32
+    L.grand_server_destroy.argtypes = [vp]
+    L.grand_server_destroy.restype = None
+    L.grand_server_submit.argtypes = [vp, vp, vp, u32, ctypes.c_float, u64,
+                                      ctypes.POINTER(u64)]
+    L.grand_server_submit.restype = i32
+    L.grand_server_cancel.argtypes = [vp, u64]
+    L.grand_server_cancel.restype = i32
+    L.grand_server_poll.argtypes = [vp, ctypes.POINTER(GrandResult), u32, ctypes.POINTER(u32)]
+    L.grand_server_poll.restype = i32
+    L.grand_server_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                     ctypes.POINTER(u64)]
+    L.grand_server_stats.restype = i32
+    L.grand_server_run_trace.argtypes = [vp, ctypes.POINTER(vp), u32,
+                                         ctypes.POINTER(GrandTraceReq), u32, vp,
+                                         ctypes.POINTER(GrandResult), ctypes.POINTER(ctypes.c_double)]
+    L.grand_server_run_trace.restype = i32
+    L.grand_plain_run_trace.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(GrandTraceReq),
+                                        u32, vp, ctypes.POINTER(GrandResult),
+                                        ctypes.POINTER(ctypes.c_double)]
+    L.grand_plain_run_trace.restype = i32
     _lib = L
     return L
 

@@ -14,19 +14,13 @@
 #include <string>
 #include <vector>
 
-#include "grand.h"
-#include "grand_internal.h"
+#include "grand_host.h"
 
 using namespace grand;
+using namespace grand::host;
 
-struct grand_code {
-    uint32_t n, rows, kw, row_w32;
-    int device;
-    uint32_t *d_rows;   // rows x row_w32
-    uint32_t *d_cols;   // n x kw
-};
-
-namespace {
+namespace grand {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -35,13 +29,6 @@ int fail(int code, const std::string &msg)
     g_last_error = msg;
     return code;
 }
-
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(GRAND_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 bool valid_m(uint32_t M)
 {
@@ -73,7 +60,7 @@ grand_tuning builtin_tuning(uint32_t n, uint32_t M)
 {
     (void)M;
     grand_tuning t;
-    t.low_bits = n <= 64 ? 8 : 9;
+    t.low_bits = (n && n <= 64) ? 8 : 9;
     t.block = 256;
     t.first_band = 256;
     t.band_growth = 4;
@@ -110,39 +97,6 @@ bool valid_tuning(const grand_tuning &t)
 }
 
 // ---------------------------------------------------------------- device context
-struct StreamRes {
-    uint8_t *scratch = nullptr;     // high-subset stores, one slot per workgroup
-    size_t scratch_bytes = 0;
-    uint32_t *queues = nullptr;     // 64 counters
-    DevJob *jobs = nullptr;
-    size_t jobs_cap = 0;
-    DevCode *codes = nullptr;
-    size_t codes_cap = 0;
-    DevJob *h_jobs = nullptr;       // pinned staging
-    size_t h_jobs_cap = 0;
-    DevCode *h_codes = nullptr;
-    size_t h_codes_cap = 0;
-    hipEvent_t staged = nullptr;
-    bool staged_pending = false;
-    // single-decode buffers
-    float *d_rx = nullptr;
-    uint64_t *d_out = nullptr;      // 16 cw words + q + checks
-    uint8_t *d_ab = nullptr;
-    int32_t *d_status = nullptr;
-    float *h_rx = nullptr;          // pinned
-    uint64_t *h_out = nullptr;      // pinned: 16 cw words, q
-    uint8_t *h_ab = nullptr;
-    int32_t *h_status = nullptr;
-};
-
-struct DeviceCtx {
-    int device = -1;
-    int cus = 0;
-    std::mutex mu;
-    hipStream_t own_stream = nullptr;
-    std::map<void *, StreamRes> res;
-};
-
 std::mutex g_ctx_mu;
 std::map<int, std::unique_ptr<DeviceCtx>> g_ctx;
 
@@ -197,9 +151,8 @@ int ensure_pinned(T **p, size_t *cap, size_t want)
     return GRAND_OK;
 }
 
-int stream_res(DeviceCtx *ctx, void *stream, StreamRes **out)
+int init_stream_res(StreamRes &r)
 {
-    StreamRes &r = ctx->res[stream];
     if (!r.queues) {
         if (hipMalloc((void **)&r.queues, 64 * sizeof(uint32_t)) != hipSuccess)
             return fail(GRAND_ENOMEM, "hipMalloc failed for work counters");
@@ -217,6 +170,15 @@ int stream_res(DeviceCtx *ctx, void *stream, StreamRes **out)
             hipHostMalloc((void **)&r.h_status, 64, hipHostMallocDefault) != hipSuccess)
             return fail(GRAND_ENOMEM, "hipHostMalloc failed for single-decode buffers");
     }
+    return GRAND_OK;
+}
+
+int stream_res(DeviceCtx *ctx, void *stream, StreamRes **out)
+{
+    StreamRes &r = ctx->res[stream];
+    int rc = init_stream_res(r);
+    if (rc)
+        return rc;
     *out = &r;
     return GRAND_OK;
 }
@@ -243,6 +205,7 @@ struct Bucket {
     uint32_t n, M;
     grand_tuning t;
     std::vector<uint32_t> words;
+    uint32_t ni = 0;   // LDS sizing: next_pow2(2L) of the bucket's largest word
 };
 
 // Enqueue one launch per bucket; jobs/codes already staged in device memory.
@@ -273,7 +236,7 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
         a.first_band = t.first_band;
         a.band_growth = t.band_growth;
         a.node_cap = t.node_cap;
-        a.ni = items_pow2(buckets[i].n, buckets[i].M);
+        a.ni = buckets[i].ni ? buckets[i].ni : items_pow2(buckets[i].n, buckets[i].M);
         a.rx = rx;
         a.cw_out = cw_out;
         a.q_out = q_out;
@@ -291,7 +254,109 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
     return GRAND_OK;
 }
 
-}  // namespace
+// Validate a batch, bucket it by (n, M), stage its jobs and enqueue the
+// launches on `stream` using the buffers of `r`.
+int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream, int mixed)
+{
+    if (!b)
+        return fail(GRAND_EINVAL, "null batch");
+    if (b->count == 0)
+        return GRAND_OK;
+    if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
+        !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
+        return fail(GRAND_EINVAL, "null pointer in batch");
+    if (b->n_codes == 0)
+        return fail(GRAND_EINVAL, "no codes");
+    for (uint32_t c = 0; c < b->n_codes; c++)
+        if (!b->codes[c] || b->codes[c]->device != ctx->device)
+            return fail(GRAND_EINVAL, "null code or code on another device");
+    std::map<std::pair<uint32_t, uint32_t>, size_t> index;
+    std::vector<Bucket> buckets;
+    for (uint32_t i = 0; i < b->count; i++) {
+        uint32_t ci = b->code_index[i];
+        if (ci >= b->n_codes)
+            return fail(GRAND_EINVAL, "code index out of range");
+        if (!valid_m(b->M[i]))
+            return fail(GRAND_EINVAL, "invalid M");
+        if (b->query_cap[i] < 1 || b->query_cap[i] > GRAND_MAX_CAP)
+            return fail(GRAND_EINVAL, "query cap out of range");
+        if (!std::isfinite(b->noise_var[i]) || b->noise_var[i] <= 0.0f)
+            return fail(GRAND_EINVAL, "noise variance must be finite and positive");
+        auto key = std::make_pair(b->codes[ci]->n, b->M[i]);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            it = index.emplace(key, buckets.size()).first;
+            buckets.push_back(Bucket{key.first, key.second, tuning_for(key.first, key.second), {}});
+        }
+        buckets[it->second].words.push_back(i);
+    }
+    // One launch for the whole batch when asked, or when no (n, M) bucket
+    // fills the device on its own: words of every size share the persistent
+    // workgroups (LDS sized for the largest), heaviest first.
+    if (buckets.size() > 1) {
+        size_t biggest = 0;
+        for (auto &bk : buckets)
+            biggest = std::max(biggest, bk.words.size());
+        if (mixed < 0)
+            mixed = biggest < (size_t)tuning_for(0, 0).grid_per_cu * ctx->cus;
+        if (mixed) {
+            Bucket all{0, 0, tuning_for(0, 0), {}};
+            for (auto &bk : buckets) {
+                all.ni = std::max(all.ni, items_pow2(bk.n, bk.M));
+                all.n = std::max(all.n, bk.n);
+                all.words.insert(all.words.end(), bk.words.begin(), bk.words.end());
+            }
+            std::stable_sort(all.words.begin(), all.words.end(), [&](uint32_t x, uint32_t y) {
+                const grand_code *cx = b->codes[b->code_index[x]], *cy = b->codes[b->code_index[y]];
+                uint32_t wx = items_pow2(cx->n, b->M[x]), wy = items_pow2(cy->n, b->M[y]);
+                if (wx != wy)
+                    return wx > wy;
+                return b->query_cap[x] > b->query_cap[y];
+            });
+            buckets.assign(1, all);
+        }
+    }
+    int rc = init_stream_res(r);
+    if (rc)
+        return rc;
+    if (r.staged_pending) {
+        HIP_TRY(hipEventSynchronize(r.staged));
+        r.staged_pending = false;
+    }
+    rc = ensure_device(&r.codes, &r.codes_cap, b->n_codes);
+    if (!rc)
+        rc = ensure_device(&r.jobs, &r.jobs_cap, b->count);
+    if (!rc)
+        rc = ensure_pinned(&r.h_codes, &r.h_codes_cap, b->n_codes);
+    if (!rc)
+        rc = ensure_pinned(&r.h_jobs, &r.h_jobs_cap, b->count);
+    if (rc)
+        return rc;
+    for (uint32_t c = 0; c < b->n_codes; c++) {
+        const grand_code *cd = b->codes[c];
+        r.h_codes[c] = DevCode{cd->n, cd->rows, cd->kw, cd->row_w32, cd->d_rows, cd->d_cols};
+    }
+    std::vector<uint32_t> job_base;
+    uint32_t k = 0;
+    for (auto &bk : buckets) {
+        job_base.push_back(k);
+        for (uint32_t i : bk.words)
+            r.h_jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i],
+                                   i, 0};
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(r.codes, r.h_codes, b->n_codes * sizeof(DevCode),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r.jobs, r.h_jobs, b->count * sizeof(DevJob), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipEventRecord(r.staged, st));
+    r.staged_pending = true;
+    return enqueue_buckets(ctx, r, buckets, job_base, b->rx, b->codeword_out, b->queries_out,
+                           b->abandoned_out, b->status_out, b->checks_out, stream);
+}
+
+}  // namespace host
+}  // namespace grand
 
 // ==================================================================== ABI
 
@@ -483,76 +548,19 @@ int grand_decode_batch(const grand_batch *b, void *stream)
     if (b->count == 0)
         return GRAND_OK;
     if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
-        !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
-        return fail(GRAND_EINVAL, "null pointer in batch");
-    if (b->n_codes == 0)
-        return fail(GRAND_EINVAL, "no codes");
+        !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out ||
+        b->n_codes == 0)
+        return fail(GRAND_EINVAL, "null pointer or no codes in batch");
     DeviceCtx *ctx;
     int rc = current_ctx(&ctx);
     if (rc)
         return rc;
-    for (uint32_t c = 0; c < b->n_codes; c++)
-        if (!b->codes[c] || b->codes[c]->device != ctx->device)
-            return fail(GRAND_EINVAL, "null code or code on another device");
-    std::map<std::pair<uint32_t, uint32_t>, size_t> index;
-    std::vector<Bucket> buckets;
-    for (uint32_t i = 0; i < b->count; i++) {
-        uint32_t ci = b->code_index[i];
-        if (ci >= b->n_codes)
-            return fail(GRAND_EINVAL, "code index out of range");
-        if (!valid_m(b->M[i]))
-            return fail(GRAND_EINVAL, "invalid M");
-        if (b->query_cap[i] < 1 || b->query_cap[i] > GRAND_MAX_CAP)
-            return fail(GRAND_EINVAL, "query cap out of range");
-        if (!std::isfinite(b->noise_var[i]) || b->noise_var[i] <= 0.0f)
-            return fail(GRAND_EINVAL, "noise variance must be finite and positive");
-        auto key = std::make_pair(b->codes[ci]->n, b->M[i]);
-        auto it = index.find(key);
-        if (it == index.end()) {
-            it = index.emplace(key, buckets.size()).first;
-            buckets.push_back(Bucket{key.first, key.second, tuning_for(key.first, key.second), {}});
-        }
-        buckets[it->second].words.push_back(i);
-    }
     std::lock_guard<std::mutex> g(ctx->mu);
     StreamRes *r;
     rc = stream_res(ctx, stream, &r);
     if (rc)
         return rc;
-    if (r->staged_pending) {
-        HIP_TRY(hipEventSynchronize(r->staged));
-        r->staged_pending = false;
-    }
-    rc = ensure_device(&r->codes, &r->codes_cap, b->n_codes);
-    if (!rc)
-        rc = ensure_device(&r->jobs, &r->jobs_cap, b->count);
-    if (!rc)
-        rc = ensure_pinned(&r->h_codes, &r->h_codes_cap, b->n_codes);
-    if (!rc)
-        rc = ensure_pinned(&r->h_jobs, &r->h_jobs_cap, b->count);
-    if (rc)
-        return rc;
-    for (uint32_t c = 0; c < b->n_codes; c++) {
-        const grand_code *cd = b->codes[c];
-        r->h_codes[c] = DevCode{cd->n, cd->rows, cd->kw, cd->row_w32, cd->d_rows, cd->d_cols};
-    }
-    std::vector<uint32_t> job_base;
-    uint32_t k = 0;
-    for (auto &bk : buckets) {
-        job_base.push_back(k);
-        for (uint32_t i : bk.words)
-            r->h_jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i],
-                                    i, 0};
-    }
-    hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(r->codes, r->h_codes, b->n_codes * sizeof(DevCode),
-                           hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(r->jobs, r->h_jobs, b->count * sizeof(DevJob), hipMemcpyHostToDevice,
-                           st));
-    HIP_TRY(hipEventRecord(r->staged, st));
-    r->staged_pending = true;
-    return enqueue_buckets(ctx, *r, buckets, job_base, b->rx, b->codeword_out, b->queries_out,
-                           b->abandoned_out, b->status_out, b->checks_out, stream);
+    return decode_batch_on(ctx, *r, b, stream, -1);
 }
 
 }  // extern "C"

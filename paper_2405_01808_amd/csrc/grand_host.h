@@ -1,0 +1,80 @@
+// grand_host.h -- host-side runtime pieces shared by grand_api.hip and
+// grand_server.hip (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "grand.h"
+#include "grand_internal.h"
+
+struct grand_code {
+    uint32_t n, rows, kw, row_w32;
+    int device;
+    uint32_t *d_rows;   // rows x row_w32
+    uint32_t *d_cols;   // n x kw
+};
+
+namespace grand {
+namespace host {
+
+// Record an error message for grand_last_error() and return `code`.
+int fail(int code, const std::string &msg);
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::grand::host::fail(GRAND_EDEVICE,                                  \
+                                       std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device buffers and pinned staging of one launch stream.
+struct StreamRes {
+    uint8_t *scratch = nullptr;     // high-subset stores, one slot per workgroup
+    size_t scratch_bytes = 0;
+    uint32_t *queues = nullptr;     // 64 work counters
+    DevJob *jobs = nullptr;
+    size_t jobs_cap = 0;
+    DevCode *codes = nullptr;
+    size_t codes_cap = 0;
+    DevJob *h_jobs = nullptr;       // pinned staging
+    size_t h_jobs_cap = 0;
+    DevCode *h_codes = nullptr;
+    size_t h_codes_cap = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    // single-decode buffers
+    float *d_rx = nullptr;
+    uint64_t *d_out = nullptr;      // 16 cw words + q + checks
+    uint8_t *d_ab = nullptr;
+    int32_t *d_status = nullptr;
+    float *h_rx = nullptr;          // pinned
+    uint64_t *h_out = nullptr;      // pinned: 16 cw words, q
+    uint8_t *h_ab = nullptr;
+    int32_t *h_status = nullptr;
+};
+
+struct DeviceCtx {
+    int device = -1;
+    int cus = 0;
+    std::mutex mu;
+    hipStream_t own_stream = nullptr;
+    std::map<void *, StreamRes> res;
+};
+
+bool valid_m(uint32_t M);
+uint32_t symbols(uint32_t n, uint32_t M);
+grand_tuning tuning_for(uint32_t n, uint32_t M);
+int current_ctx(DeviceCtx **out);
+int init_stream_res(StreamRes &r);
+// mixed: 1 = one launch for all words, 0 = one launch per (n, M) bucket,
+// -1 = one launch when no bucket fills the device on its own.
+int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream,
+                    int mixed);
+
+}  // namespace host
+}  // namespace grand

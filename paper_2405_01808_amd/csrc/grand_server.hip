@@ -1,0 +1,505 @@
+// grand_server.hip -- continuously batched serving of decode requests, and
+// real-time replay of recorded arrival streams (server and plain paths).
+//
+// Requests are admitted within a slot count and a device-memory budget.
+// Each lane is one HIP stream with its own staging and device buffers; when
+// a lane is idle, every admitted request not yet launched is copied to it
+// and decoded as one batch (grand_decode_batch's path), so batches launched
+// at different times overlap on the device.  Completion is observed with
+// stream events; results are copied back asynchronously into pinned memory
+// before the event, so harvesting never blocks.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "grand_host.h"
+
+using namespace grand;
+using namespace grand::host;
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    uint64_t id;
+    const grand_code *code;
+    uint32_t M;
+    uint64_t cap;
+    float noise_var;
+    std::vector<float> rx;
+    double arrival_s, submit_s;
+    uint64_t bytes;
+};
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    StreamRes res;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    uint32_t cap = 0;                 // requests the buffers hold
+    // device
+    float *d_rx = nullptr;
+    uint64_t *d_cw = nullptr, *d_q = nullptr, *d_chk = nullptr;
+    uint8_t *d_ab = nullptr;
+    int32_t *d_st = nullptr;
+    // pinned
+    float *h_rx = nullptr;
+    uint64_t *h_cw = nullptr, *h_q = nullptr, *h_chk = nullptr;
+    uint8_t *h_ab = nullptr;
+    int32_t *h_st = nullptr;
+    std::vector<Request> reqs;        // the batch on the device
+};
+
+}  // namespace
+
+struct grand_server {
+    grand_server_config cfg;
+    DeviceCtx *ctx = nullptr;
+    std::mutex mu;
+    std::deque<Request> pending;
+    std::vector<std::unique_ptr<Lane>> lanes;
+    std::deque<grand_result> done;
+    uint64_t next_id = 1;
+    uint64_t inflight = 0;            // admitted and not yet returned
+    uint64_t running = 0;             // on the device
+    uint64_t mem_in_use = 0;
+};
+
+namespace {
+
+int lane_init(Lane &L, uint32_t cap)
+{
+    HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+    L.cap = cap;
+    const size_t rxf = (size_t)cap * 2 * kMaxItems;
+    if (hipMalloc((void **)&L.d_rx, rxf * sizeof(float)) != hipSuccess ||
+        hipMalloc((void **)&L.d_cw, (size_t)cap * kCwStride * 8) != hipSuccess ||
+        hipMalloc((void **)&L.d_q, (size_t)cap * 8) != hipSuccess ||
+        hipMalloc((void **)&L.d_chk, (size_t)cap * 8) != hipSuccess ||
+        hipMalloc((void **)&L.d_ab, cap) != hipSuccess ||
+        hipMalloc((void **)&L.d_st, (size_t)cap * 4) != hipSuccess)
+        return fail(GRAND_ENOMEM, "hipMalloc failed for server lane buffers");
+    if (hipHostMalloc((void **)&L.h_rx, rxf * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&L.h_cw, (size_t)cap * kCwStride * 8, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&L.h_q, (size_t)cap * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&L.h_chk, (size_t)cap * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&L.h_ab, cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&L.h_st, (size_t)cap * 4, hipHostMallocDefault) != hipSuccess)
+        return fail(GRAND_ENOMEM, "hipHostMalloc failed for server lane buffers");
+    return init_stream_res(L.res);
+}
+
+void lane_free(Lane &L)
+{
+    if (L.stream)
+        (void)hipStreamSynchronize(L.stream);
+    (void)hipFree(L.d_rx);
+    (void)hipFree(L.d_cw);
+    (void)hipFree(L.d_q);
+    (void)hipFree(L.d_chk);
+    (void)hipFree(L.d_ab);
+    (void)hipFree(L.d_st);
+    (void)hipHostFree(L.h_rx);
+    (void)hipHostFree(L.h_cw);
+    (void)hipHostFree(L.h_q);
+    (void)hipHostFree(L.h_chk);
+    (void)hipHostFree(L.h_ab);
+    (void)hipHostFree(L.h_st);
+    StreamRes &r = L.res;
+    (void)hipFree(r.scratch);
+    (void)hipFree(r.queues);
+    (void)hipFree(r.jobs);
+    (void)hipFree(r.codes);
+    (void)hipHostFree(r.h_jobs);
+    (void)hipHostFree(r.h_codes);
+    (void)hipFree(r.d_rx);
+    (void)hipFree(r.d_out);
+    (void)hipFree(r.d_ab);
+    (void)hipFree(r.d_status);
+    (void)hipHostFree(r.h_rx);
+    (void)hipHostFree(r.h_out);
+    (void)hipHostFree(r.h_ab);
+    (void)hipHostFree(r.h_status);
+    if (r.staged)
+        (void)hipEventDestroy(r.staged);
+    if (L.done)
+        (void)hipEventDestroy(L.done);
+    if (L.stream)
+        (void)hipStreamDestroy(L.stream);
+}
+
+// Move every pending request (up to the lane's capacity) onto an idle lane.
+int lane_launch(grand_server *s, Lane &L)
+{
+    const uint32_t B = (uint32_t)std::min<size_t>(s->pending.size(), L.cap);
+    if (B == 0)
+        return GRAND_OK;
+    L.reqs.clear();
+    std::vector<const grand_code *> codes;
+    std::vector<uint32_t> code_index(B), Mv(B);
+    std::vector<uint64_t> capv(B), offs(B);
+    std::vector<float> nvv(B);
+    std::map<const grand_code *, uint32_t> cidx;
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < B; i++) {
+        Request &q = s->pending.front();
+        auto it = cidx.find(q.code);
+        if (it == cidx.end()) {
+            it = cidx.emplace(q.code, (uint32_t)codes.size()).first;
+            codes.push_back(q.code);
+        }
+        code_index[i] = it->second;
+        Mv[i] = q.M;
+        capv[i] = q.cap;
+        nvv[i] = q.noise_var;
+        offs[i] = off;
+        std::memcpy(L.h_rx + off, q.rx.data(), q.rx.size() * sizeof(float));
+        off += q.rx.size();
+        L.reqs.push_back(std::move(q));
+        s->pending.pop_front();
+    }
+    HIP_TRY(hipMemcpyAsync(L.d_rx, L.h_rx, off * sizeof(float), hipMemcpyHostToDevice, L.stream));
+    grand_batch b;
+    b.count = B;
+    b.n_codes = (uint32_t)codes.size();
+    b.codes = codes.data();
+    b.code_index = code_index.data();
+    b.M = Mv.data();
+    b.query_cap = capv.data();
+    b.noise_var = nvv.data();
+    b.rx_offset = offs.data();
+    b.rx = L.d_rx;
+    b.codeword_out = L.d_cw;
+    b.queries_out = L.d_q;
+    b.abandoned_out = L.d_ab;
+    b.status_out = L.d_st;
+    b.checks_out = L.d_chk;
+    int rc = decode_batch_on(s->ctx, L.res, &b, L.stream, 1);
+    if (rc) {   // return the batch as failed requests instead of losing it
+        const double t = now_s();
+        for (const Request &q : L.reqs) {
+            grand_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.request_id = q.id;
+            r.status = rc;
+            r.abandoned = 1;
+            r.arrival_s = q.arrival_s;
+            r.submit_s = q.submit_s;
+            r.complete_s = t;
+            s->done.push_back(r);
+            s->mem_in_use -= q.bytes;
+            s->inflight--;
+        }
+        L.reqs.clear();
+        return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(L.h_cw, L.d_cw, (size_t)B * kCwStride * 8, hipMemcpyDeviceToHost,
+                           L.stream));
+    HIP_TRY(hipMemcpyAsync(L.h_q, L.d_q, (size_t)B * 8, hipMemcpyDeviceToHost, L.stream));
+    HIP_TRY(hipMemcpyAsync(L.h_chk, L.d_chk, (size_t)B * 8, hipMemcpyDeviceToHost, L.stream));
+    HIP_TRY(hipMemcpyAsync(L.h_ab, L.d_ab, B, hipMemcpyDeviceToHost, L.stream));
+    HIP_TRY(hipMemcpyAsync(L.h_st, L.d_st, (size_t)B * 4, hipMemcpyDeviceToHost, L.stream));
+    HIP_TRY(hipEventRecord(L.done, L.stream));
+    L.busy = true;
+    s->running += B;
+    return GRAND_OK;
+}
+
+// Collect a finished lane's results.
+void lane_harvest(grand_server *s, Lane &L, double t)
+{
+    for (size_t i = 0; i < L.reqs.size(); i++) {
+        const Request &q = L.reqs[i];
+        grand_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.request_id = q.id;
+        std::memcpy(r.codeword, L.h_cw + i * kCwStride, ((q.code->n + 63) / 64) * 8);
+        r.queries = L.h_q[i];
+        r.checks = L.h_chk[i];
+        r.status = L.h_st[i];
+        r.abandoned = L.h_ab[i];
+        r.arrival_s = q.arrival_s;
+        r.submit_s = q.submit_s;
+        r.complete_s = t;
+        s->done.push_back(r);
+        s->mem_in_use -= q.bytes;
+        s->inflight--;
+    }
+    s->running -= L.reqs.size();
+    L.reqs.clear();
+    L.busy = false;
+}
+
+int validate_request(const grand_code *code, const float *rx, uint32_t M, float noise_var,
+                     uint64_t cap)
+{
+    if (!code || !rx)
+        return fail(GRAND_EINVAL, "null pointer");
+    if (!valid_m(M))
+        return fail(GRAND_EINVAL, "M must be 4, 16, 64, 256, 1024 or 4096");
+    if (cap < 1 || cap > GRAND_MAX_CAP)
+        return fail(GRAND_EINVAL, "query cap out of range");
+    if (!std::isfinite(noise_var) || noise_var <= 0.0f)
+        return fail(GRAND_EINVAL, "noise variance must be finite and positive");
+    const uint32_t L = symbols(code->n, M);
+    for (uint32_t i = 0; i < 2 * L; i++)
+        if (!std::isfinite(rx[i]) || std::fabs(rx[i]) > 32768.0f)
+            return fail(GRAND_EINVAL, "received value not finite or beyond 2^15");
+    return GRAND_OK;
+}
+
+int submit_locked(grand_server *s, const grand_code *code, const float *rx, uint32_t M,
+                  float noise_var, uint64_t cap, double arrival, uint64_t *id)
+{
+    int rc = validate_request(code, rx, M, noise_var, cap);
+    if (rc)
+        return rc;
+    if (code->device != s->ctx->device)
+        return fail(GRAND_EINVAL, "code was created on another device");
+    const uint64_t bytes = grand_request_bytes(code->n, M);
+    if (s->inflight + 1 > s->cfg.max_inflight || s->mem_in_use + bytes > s->cfg.memory_budget)
+        return fail(GRAND_EBUSY, "admission refused: slots or memory budget exhausted");
+    Request q;
+    q.id = s->next_id++;
+    q.code = code;
+    q.M = M;
+    q.cap = cap;
+    q.noise_var = noise_var;
+    q.rx.assign(rx, rx + 2 * symbols(code->n, M));
+    q.submit_s = now_s();
+    q.arrival_s = arrival > 0 ? arrival : q.submit_s;
+    q.bytes = bytes;
+    s->pending.push_back(std::move(q));
+    s->inflight++;
+    s->mem_in_use += bytes;
+    if (id)
+        *id = s->pending.back().id;
+    return GRAND_OK;
+}
+
+int poll_locked(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *n_out)
+{
+    const double t = now_s();
+    for (auto &L : s->lanes) {
+        if (!L->busy)
+            continue;
+        hipError_t e = hipEventQuery(L->done);
+        if (e == hipSuccess)
+            lane_harvest(s, *L, t);
+        else if (e != hipErrorNotReady)
+            return fail(GRAND_EDEVICE, std::string("server lane: ") + hipGetErrorString(e));
+    }
+    for (auto &L : s->lanes) {
+        if (s->pending.empty())
+            break;
+        if (!L->busy) {
+            int rc = lane_launch(s, *L);
+            if (rc)
+                return rc;
+        }
+    }
+    uint32_t k = 0;
+    while (k < max_out && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    if (n_out)
+        *n_out = k;
+    return GRAND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t grand_request_bytes(uint32_t n, uint32_t M)
+{
+    if (n < 2 || n > kMaxN || (n & (n - 1)) || !valid_m(M))
+        return 0;
+    const grand_tuning t = tuning_for(n, M);
+    return 2ull * symbols(n, M) * sizeof(float) + (kCwStride + 3) * 8 +
+           node_layout(t.node_cap).total;
+}
+
+int grand_server_create(const grand_server_config *cfg, grand_server **out)
+{
+    if (!cfg || !out)
+        return fail(GRAND_EINVAL, "null pointer");
+    if (cfg->max_inflight < 1 || cfg->max_inflight > (1u << 20) || cfg->lanes < 1 ||
+        cfg->lanes > 8 || cfg->max_batch < 1 || cfg->max_batch > 65536 ||
+        cfg->memory_budget == 0)
+        return fail(GRAND_EINVAL, "invalid server configuration");
+    DeviceCtx *ctx;
+    int rc = current_ctx(&ctx);
+    if (rc)
+        return rc;
+    auto s = std::make_unique<grand_server>();
+    s->cfg = *cfg;
+    s->ctx = ctx;
+    const uint32_t per_lane = std::min(cfg->max_batch, cfg->max_inflight);
+    for (uint32_t i = 0; i < cfg->lanes; i++) {
+        auto L = std::make_unique<Lane>();
+        rc = lane_init(*L, per_lane);
+        if (rc) {
+            lane_free(*L);
+            for (auto &x : s->lanes)
+                lane_free(*x);
+            return rc;
+        }
+        s->lanes.push_back(std::move(L));
+    }
+    *out = s.release();
+    return GRAND_OK;
+}
+
+void grand_server_destroy(grand_server *s)
+{
+    if (!s)
+        return;
+    for (auto &L : s->lanes)
+        lane_free(*L);
+    delete s;
+}
+
+int grand_server_submit(grand_server *s, const grand_code *code, const float *rx, uint32_t M,
+                        float noise_var, uint64_t query_cap, uint64_t *request_id)
+{
+    if (!s)
+        return fail(GRAND_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    return submit_locked(s, code, rx, M, noise_var, query_cap, 0.0, request_id);
+}
+
+int grand_server_cancel(grand_server *s, uint64_t request_id)
+{
+    if (!s)
+        return fail(GRAND_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+        if (it->id == request_id) {
+            s->mem_in_use -= it->bytes;
+            s->inflight--;
+            s->pending.erase(it);
+            return GRAND_OK;
+        }
+    }
+    return fail(GRAND_ENOTFOUND, "request not pending (unknown, launched or finished)");
+}
+
+int grand_server_poll(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *n_out)
+{
+    if (!s || (max_out && !out))
+        return fail(GRAND_EINVAL, "null pointer");
+    std::lock_guard<std::mutex> g(s->mu);
+    return poll_locked(s, out, max_out, n_out);
+}
+
+int grand_server_stats(grand_server *s, uint64_t *pending, uint64_t *running,
+                       uint64_t *memory_in_use)
+{
+    if (!s)
+        return fail(GRAND_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    if (pending)
+        *pending = s->pending.size();
+    if (running)
+        *running = s->running;
+    if (memory_in_use)
+        *memory_in_use = s->mem_in_use;
+    return GRAND_OK;
+}
+
+int grand_server_run_trace(grand_server *s, const grand_code *const *codes, uint32_t n_codes,
+                           const grand_trace_req *reqs, uint32_t count, const float *rx,
+                           grand_result *results, double *wall_s)
+{
+    if (!s || !codes || !reqs || !rx || !results || n_codes == 0)
+        return fail(GRAND_EINVAL, "null pointer");
+    for (uint32_t i = 0; i < count; i++)
+        if (reqs[i].code_index >= n_codes || !codes[reqs[i].code_index])
+            return fail(GRAND_EINVAL, "trace request with a bad code index");
+    std::unordered_map<uint64_t, uint32_t> slot_of;
+    std::vector<grand_result> buf(1024);
+    const double t0 = now_s();
+    uint32_t next = 0, completed = 0;
+    std::lock_guard<std::mutex> g(s->mu);
+    while (completed < count) {
+        const double t = now_s() - t0;
+        while (next < count && reqs[next].arrival_s <= t) {
+            const grand_trace_req &r = reqs[next];
+            uint64_t id = 0;
+            int rc = submit_locked(s, codes[r.code_index], rx + r.rx_offset, r.M, r.noise_var,
+                                   r.query_cap, t0 + r.arrival_s, &id);
+            if (rc == GRAND_EBUSY)
+                break;           // retried once completions free room
+            if (rc)
+                return rc;
+            slot_of[id] = next++;
+        }
+        uint32_t got = 0;
+        int rc = poll_locked(s, buf.data(), (uint32_t)buf.size(), &got);
+        if (rc)
+            return rc;
+        for (uint32_t k = 0; k < got; k++) {
+            auto it = slot_of.find(buf[k].request_id);
+            if (it == slot_of.end())
+                continue;        // a request submitted outside this replay
+            results[it->second] = buf[k];
+            slot_of.erase(it);
+            completed++;
+        }
+    }
+    if (wall_s)
+        *wall_s = now_s() - t0;
+    return GRAND_OK;
+}
+
+int grand_plain_run_trace(const grand_code *const *codes, uint32_t n_codes,
+                          const grand_trace_req *reqs, uint32_t count, const float *rx,
+                          grand_result *results, double *wall_s)
+{
+    if (!codes || !reqs || !rx || !results || n_codes == 0)
+        return fail(GRAND_EINVAL, "null pointer");
+    const double t0 = now_s();
+    for (uint32_t i = 0; i < count; i++) {
+        const grand_trace_req &r = reqs[i];
+        if (r.code_index >= n_codes || !codes[r.code_index])
+            return fail(GRAND_EINVAL, "trace request with a bad code index");
+        while (now_s() - t0 < r.arrival_s) {
+        }
+        grand_result &o = results[i];
+        std::memset(&o, 0, sizeof(o));
+        o.request_id = i + 1;
+        o.arrival_s = t0 + r.arrival_s;
+        o.submit_s = now_s();
+        int rc = grand_decode(codes[r.code_index], rx + r.rx_offset, r.M, r.noise_var,
+                              r.query_cap, o.codeword, &o.queries, &o.abandoned);
+        if (rc)
+            return rc;
+        o.checks = 0;
+        o.status = GRAND_OK;
+        o.complete_s = now_s();
+    }
+    if (wall_s)
+        *wall_s = now_s() - t0;
+    return GRAND_OK;
+}
+
+}  // extern "C"

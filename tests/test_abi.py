@@ -92,3 +92,27 @@ def test_tuning_table_roundtrip_and_validation():
         g.set_tuning(2, 4096, block=64, low_bits=10)
     with pytest.raises(g.GrandError):
         g.set_tuning(2, 4096, block=512)
+
+
+def test_server_configuration_rejected_on_host():
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    out = ctypes.c_void_p()
+    for cfg in [(0, 1, 1, 1 << 20), (4, 0, 1, 1 << 20), (4, 9, 1, 1 << 20), (4, 1, 0, 1 << 20),
+                (4, 1, 1, 0), ((1 << 20) + 1, 1, 1, 1 << 20)]:
+        c = nat.GrandServerConfig(cfg[0], cfg[1], cfg[2], 0, cfg[3])
+        assert L.grand_server_create(ctypes.byref(c), ctypes.byref(out)) == nat.GRAND_EINVAL
+    assert L.grand_server_create(None, ctypes.byref(out)) == nat.GRAND_EINVAL
+    assert L.grand_server_submit(None, None, None, 4, 1.0, 1, None) == nat.GRAND_EINVAL
+    assert L.grand_server_poll(None, None, 0, None) == nat.GRAND_EINVAL
+    assert L.grand_server_cancel(None, 1) == nat.GRAND_EINVAL
+
+
+def test_request_bytes_reflects_tuned_store():
+    import paper_2405_01808_amd as g
+    from paper_2405_01808_amd import _native as nat
+    assert nat.lib().grand_request_bytes(48, 4) == 0
+    assert nat.lib().grand_request_bytes(32, 8) == 0
+    b = g.request_bytes(1024, 4)
+    t = g.get_tuning(1024, 4)
+    assert b > 18 * t["node_cap"]
