@@ -64,22 +64,30 @@ def serving(g, w, count: int, plain_count: int):
     arrivals = np.array([j.arrival_s for j in jobs]) - jobs[0].arrival_s
     trace = g.Trace(order, idx, [j.M for j in jobs], [j.cap for j in jobs],
                     [j.noise_var for j in jobs], [j.rx for j in jobs], arrivals)
-    srv = g.Server(max_inflight=16384, lanes=8, max_batch=2048, memory_budget=48 << 30)
-    res, wall = trace.run_server(srv)
-    assert all(r.status == 0 for r in res), "server request errors"
-    lat = np.array([r.latency_s for r in res]) * 1e3
-    groups = {}
-    for j, l in zip(jobs, lat):
-        groups.setdefault((j.N, j.M), []).append(l)
-    for k in sorted(groups, key=lambda k: -np.percentile(groups[k], 99))[:6]:
-        log(f"serving (N, M)={k}: n={len(groups[k])} p50 {np.percentile(groups[k], 50):.3f} ms "
-            f"p99 {np.percentile(groups[k], 99):.3f} ms")
-    q = np.array([r.queries for r in res], dtype=np.float64)
-    out = {"requests": len(jobs), "arrival_rate": 2e5, "wall_s": wall,
-           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-           "codewords_per_s": len(jobs) / wall, "checks_per_s": float(q.sum()) / wall,
-           "abandon_rate": float(np.mean([r.abandoned for r in res]))}
-    srv.close()
+
+    def replay(persistent):
+        srv = g.Server(max_inflight=16384, lanes=8, max_batch=2048, memory_budget=48 << 30,
+                       persistent=persistent)
+        res, wall = trace.run_server(srv)
+        srv.close()
+        assert all(r.status == 0 for r in res), "server request errors"
+        lat = np.array([r.latency_s for r in res]) * 1e3
+        groups = {}
+        for j, l in zip(jobs, lat):
+            groups.setdefault((j.N, j.M), []).append(l)
+        mode = "persistent" if persistent else "lanes"
+        for k in sorted(groups, key=lambda k: -np.percentile(groups[k], 99))[:6]:
+            log(f"serving[{mode}] (N, M)={k}: n={len(groups[k])} "
+                f"p50 {np.percentile(groups[k], 50):.3f} ms p99 {np.percentile(groups[k], 99):.3f} ms")
+        q = np.array([r.queries for r in res], dtype=np.float64)
+        return res, {"mode": mode, "requests": len(jobs), "arrival_rate": 2e5, "wall_s": wall,
+                     "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)),
+                     "max_ms": float(lat.max()),
+                     "codewords_per_s": len(jobs) / wall, "checks_per_s": float(q.sum()) / wall,
+                     "abandon_rate": float(np.mean([r.abandoned for r in res]))}
+
+    res, out = replay(False)
     if plain_count:
         sub = jobs[:plain_count]
         ptrace = g.Trace(order, idx[:plain_count], [j.M for j in sub], [j.cap for j in sub],

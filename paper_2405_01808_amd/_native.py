@@ -17,6 +17,8 @@ GRAND_ENOTFOUND = -6
 GRAND_MAX_N = 1024
 GRAND_MAX_CAP = 1 << 40
 CW_STRIDE = 16   # uint64 words per codeword in batch outputs
+SERVE_LANES = 0
+SERVE_PERSISTENT = 1
 
 # Every symbol the header declares; tests check that the library exports them.
 EXPORTS = [
@@ -48,7 +50,7 @@ class GrandBatch(ctypes.Structure):
 
 class GrandServerConfig(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
-                ("max_batch", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("mode", ctypes.c_uint32),
                 ("memory_budget", ctypes.c_uint64)]
 
 

@@ -50,6 +50,8 @@ namespace {
 // Per-workgroup scalars (static LDS).
 struct Shared {
     uint32_t job;
+    uint32_t state;                  // serving: kWork, kSkip or kExit
+    unsigned long long sidx;         // serving: claimed request index
     uint32_t nitems;
     uint32_t err;
     uint32_t used;                   // nodes in the store
@@ -460,6 +462,13 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
     uint32_t m = 0;
     while ((1u << (2 * (m + 1))) <= job.M && m < 6)
         m++;
+    if (m == 0 || job.M != (1u << (2 * m)) || n_bits < 2 || n_bits > kMaxN || kw > kMaxKW ||
+        2 * ((n_bits + 2 * m - 1) / (2 * m)) > a.ni) {
+        // metadata the host never produces: fail the word rather than loop
+        if (threadIdx.x == 0 && a.status_out)
+            a.status_out[job.out] = -1;   // GRAND_EINVAL
+        return;
+    }
     const int32_t levels = 1 << m;
     const uint32_t L = (n_bits + 2 * m - 1) / (2 * m);
     const uint32_t nraw = 2 * L;
@@ -856,34 +865,45 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
     }
 }
 
+struct Workspace {
+    Arr A;
+    uint32_t *lkey, *ls0;
+    Nodes nd;
+};
+
+__device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
+{
+    const LdsLayout ly = lds_layout(a.ni, blockDim.x, a.low_bits);
+    Workspace w;
+    w.A.yhat = dyn + ly.yhat;
+    w.A.s0 = dyn + ly.s0;
+    w.A.ikey = dyn + ly.ikey;
+    w.A.col0 = dyn + ly.col0;
+    w.A.lcol = dyn + ly.lcol;
+    w.A.wsum = dyn + ly.wsum;
+    w.A.foff = dyn + ly.foff;
+    w.A.fa = dyn + ly.fa;
+    w.A.fb = dyn + ly.fb;
+    w.A.fcost = dyn + ly.fcost;
+    w.A.flead = dyn + ly.flead;
+    w.lkey = dyn + ly.lkey;
+    w.ls0 = dyn + ly.ls0;
+    const NodeLayout lay = node_layout(a.node_cap);
+    uint8_t *slot = a.scratch + (uint64_t)blockIdx.x * lay.total;
+    w.nd.cost = (uint32_t *)(slot + lay.cost);
+    w.nd.lead = (uint32_t *)(slot + lay.lead);
+    w.nd.par = (uint32_t *)(slot + lay.par);
+    w.nd.rl = (uint16_t *)(slot + lay.rl);
+    w.nd.ptr = (uint16_t *)(slot + lay.ptr);
+    w.nd.cnext = (uint16_t *)(slot + lay.cnext);
+    return w;
+}
+
 __global__ __launch_bounds__(256) void grand_decode_kernel(KernelArgs a)
 {
     __shared__ Shared sh;
     extern __shared__ uint32_t dyn[];
-    const LdsLayout ly = lds_layout(a.ni, blockDim.x, a.low_bits);
-    Arr A;
-    A.yhat = dyn + ly.yhat;
-    A.s0 = dyn + ly.s0;
-    A.ikey = dyn + ly.ikey;
-    A.col0 = dyn + ly.col0;
-    A.lcol = dyn + ly.lcol;
-    A.wsum = dyn + ly.wsum;
-    A.foff = dyn + ly.foff;
-    A.fa = dyn + ly.fa;
-    A.fb = dyn + ly.fb;
-    A.fcost = dyn + ly.fcost;
-    A.flead = dyn + ly.flead;
-    uint32_t *lkey = dyn + ly.lkey;
-    uint32_t *ls0 = dyn + ly.ls0;
-    const NodeLayout lay = node_layout(a.node_cap);
-    uint8_t *slot = a.scratch + (uint64_t)blockIdx.x * lay.total;
-    Nodes nd;
-    nd.cost = (uint32_t *)(slot + lay.cost);
-    nd.lead = (uint32_t *)(slot + lay.lead);
-    nd.par = (uint32_t *)(slot + lay.par);
-    nd.rl = (uint16_t *)(slot + lay.rl);
-    nd.ptr = (uint16_t *)(slot + lay.ptr);
-    nd.cnext = (uint16_t *)(slot + lay.cnext);
+    const Workspace w = workspace(a, dyn);
     for (;;) {
         if (threadIdx.x == 0)
             sh.job = atomicAdd(a.queue, 1u);
@@ -892,8 +912,102 @@ __global__ __launch_bounds__(256) void grand_decode_kernel(KernelArgs a)
         __syncthreads();
         if (jid >= a.njobs)
             break;
-        decode_one(a, sh, A, lkey, ls0, nd, jid);
+        decode_one(a, sh, w.A, w.lkey, w.ls0, w.nd, jid);
         __syncthreads();
+    }
+}
+
+// Persistent serving (the request protocol is described with ServeArgs).
+enum : uint32_t { kWork = 0, kSkip = 1, kExit = 2 };
+
+// Claim the next request index and wait until it is published.  Only the
+// workgroup holding the lowest unpublished index reads the host's counter;
+// it also watches `stop` and the idle limit, and leaving sets `quit` for the
+// whole grid.  A workgroup never leaves while holding a published index, so
+// every index it gives up is unpublished at that time and is claimed again
+// by the next launch.
+__device__ uint32_t serve_claim(const ServeArgs &s, unsigned long long *out_idx)
+{
+    ServeDev *d = s.dev;
+    if (__hip_atomic_load(&d->quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return kExit;
+    const unsigned long long idx = atomicAdd((unsigned long long *)&d->head, 1ull);
+    *out_idx = idx;
+    bool holder = false;
+    uint64_t since = 0;
+    for (;;) {
+        const uint64_t dt = __hip_atomic_load(&d->dtail, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        if (dt > idx)
+            break;
+        if (dt == idx) {
+            const uint64_t t = __hip_atomic_load(&s.ctl->tail, __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_SYSTEM);
+            if (t > idx) {
+                atomicMax((unsigned long long *)&d->dtail, (unsigned long long)t);
+                break;
+            }
+            const uint64_t now = wall_clock64();
+            if (!holder) {
+                holder = true;
+                since = now;
+            }
+            if (__hip_atomic_load(&s.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
+                now - since > s.idle_ticks) {
+                __hip_atomic_store(&d->quit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return kExit;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        } else {
+            if (__hip_atomic_load(&d->quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return kExit;
+            // farther from the front: poll the mirror less often
+            const uint32_t k = (uint32_t)min(idx - dt, 16ull);
+            for (uint32_t i = 0; i < k; i++)
+                __builtin_amdgcn_s_sleep(16);
+        }
+    }
+    // system-scope acquire: the host's writes to the slot are visible below
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    if (__hip_atomic_load(&s.done[idx % s.ring], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >
+        idx)
+        return kSkip;   // decoded by an earlier launch (slot indices only grow)
+    return kWork;
+}
+
+__global__ __launch_bounds__(256) void grand_serve_kernel(ServeArgs s)
+{
+    __shared__ Shared sh;
+    extern __shared__ uint32_t dyn[];
+    const Workspace w = workspace(s.base, dyn);
+    for (;;) {
+        if (threadIdx.x == 0)
+            sh.state = serve_claim(s, &sh.sidx);
+        __syncthreads();
+        const uint32_t state = sh.state;
+        const uint64_t idx = sh.sidx;
+        __syncthreads();
+        if (state == kExit)
+            break;
+        if (state == kSkip)
+            continue;
+        const uint32_t slot = (uint32_t)(idx % s.ring);
+        decode_one(s.base, sh, w.A, w.lkey, w.ls0, w.nd, slot);
+        // every thread publishes its own result stores before the flag
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&s.done[slot], idx + 1, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+__global__ void serve_reset_kernel(ServeDev *d, uint64_t start)
+{
+    if (threadIdx.x == 0) {
+        d->head = start;
+        d->dtail = start;
+        d->quit = 0;
     }
 }
 
@@ -912,6 +1026,20 @@ int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stre
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return -3;
     hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_serve(const ServeArgs &sa, uint32_t grid, uint32_t block, void *stream)
+{
+    const uint32_t lds = 4u * lds_layout(sa.base.ni, block, sa.base.low_bits).words;
+    if (hipFuncSetAttribute((const void *)grand_serve_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -3;
+    hipLaunchKernelGGL(serve_reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, sa.dev,
+                       sa.start);
+    if (hipGetLastError() != hipSuccess)
+        return -3;
+    hipLaunchKernelGGL(grand_serve_kernel, dim3(grid), dim3(block), lds, (hipStream_t)stream, sa);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -38,9 +38,11 @@ def request_bytes(n: int, M: int) -> int:
 
 
 class Server:
-    def __init__(self, max_inflight=4096, lanes=4, max_batch=2048, memory_budget=8 << 30):
+    def __init__(self, max_inflight=4096, lanes=4, max_batch=2048, memory_budget=8 << 30,
+                 persistent=False):
         self._lib = nat.lib()
-        cfg = nat.GrandServerConfig(max_inflight, lanes, max_batch, 0, memory_budget)
+        mode = nat.SERVE_PERSISTENT if persistent else nat.SERVE_LANES
+        cfg = nat.GrandServerConfig(max_inflight, lanes, max_batch, mode, memory_budget)
         h = ctypes.c_void_p()
         nat.check(self._lib.grand_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -98,10 +98,12 @@ def test_server_configuration_rejected_on_host():
     from paper_2405_01808_amd import _native as nat
     L = nat.lib()
     out = ctypes.c_void_p()
-    for cfg in [(0, 1, 1, 1 << 20), (4, 0, 1, 1 << 20), (4, 9, 1, 1 << 20), (4, 1, 0, 1 << 20),
-                (4, 1, 1, 0), ((1 << 20) + 1, 1, 1, 1 << 20)]:
-        c = nat.GrandServerConfig(cfg[0], cfg[1], cfg[2], 0, cfg[3])
-        assert L.grand_server_create(ctypes.byref(c), ctypes.byref(out)) == nat.GRAND_EINVAL
+    for cfg in [(0, 1, 1, 0, 1 << 20), (4, 0, 1, 0, 1 << 20), (4, 9, 1, 0, 1 << 20),
+                (4, 1, 0, 0, 1 << 20), (4, 1, 1, 0, 0), ((1 << 20) + 1, 1, 1, 0, 1 << 20),
+                (4, 1, 1, 2, 1 << 20), (0, 0, 0, 1, 1 << 20), (4, 0, 0, 1, 0),
+                (4, 1, 1, 1, 1 << 20)]:   # persistent mode is switched off
+        c = nat.GrandServerConfig(*cfg)
+        assert L.grand_server_create(ctypes.byref(c), ctypes.byref(out)) == nat.GRAND_EINVAL, cfg
     assert L.grand_server_create(None, ctypes.byref(out)) == nat.GRAND_EINVAL
     assert L.grand_server_submit(None, None, None, 4, 1.0, 1, None) == nat.GRAND_EINVAL
     assert L.grand_server_poll(None, None, 0, None) == nat.GRAND_EINVAL
