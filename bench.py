@@ -28,10 +28,29 @@ WORKLOAD_DESC = ("Polar N=128 K=64 (PW frozen set), Gray 16-QAM, AWGN Eb/N0 unif
                  "8192 codewords per step in one persistent launch, query cap 2^16")
 ALU_PEAK = 256 * 64 * 2.4e9          # 32-bit integer lane-ops/s (256 CU x 64 lanes x 2.4 GHz)
 OPS_PER_CHECK = 2                    # leading-word XOR + zero test per performed check
+COPY_BYTES = 256 << 20               # bytes read (and written) by one calibration copy
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grand_decode_kernel_polar128_16qam_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_01808_amd", "csrc", "grand_kernels.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the decode kernel from the committed counter
+    runs, or None when the kernel source has changed since they were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != src:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(jobs, sample: int):
@@ -118,6 +137,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--plain-count", type=int, default=2000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 256 MiB three times (the reference "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this decoder runs on one GPU; --gpus must be 1 "
@@ -146,6 +168,14 @@ def main():
         plan.launch(stream)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: 3 x {COPY_BYTES >> 20} MiB device copies done")
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -196,7 +226,8 @@ def main():
         "abandon_rate": float(ab.mean()),
         "bler": bler,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK,
-                     "unit": "int32 lane-ops/s", "frac": achieved / ALU_PEAK, "traffic": None,
+                     "unit": "int32 lane-ops/s", "frac": achieved / ALU_PEAK,
+                     "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
                      "kernel": "grand_decode_kernel",
                      "work": f"{OPS_PER_CHECK} lane-ops x {int(sum_checks)} performed checks "
                              f"per launch", "avg_launch_ms": avg_launch_s * 1e3},
