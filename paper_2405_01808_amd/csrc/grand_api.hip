@@ -65,7 +65,7 @@ grand_tuning builtin_tuning(uint32_t n, uint32_t M)
     t.first_band = 256;
     t.band_growth = 4;
     t.node_cap = 1u << 16;
-    t.grid_per_cu = 6;
+    t.grid_per_cu = 8;
     return t;
 }
 

@@ -79,9 +79,12 @@ constexpr uint32_t kMergePer = 8;    // low-table merge outputs per thread and l
 // Dynamic LDS of the decode kernel, in 32-bit words: the hard word and its
 // syndrome, the ranked flips and their columns' leading words (ni each),
 // the low flips' columns, scan partials, per-slot staging of a block of
-// nodes, and the low table (keys and leading syndrome words, 2^b each).
+// nodes (one per thread), run owners, bucket indexes of the ranked
+// flips and of the low table, and the low table (keys and leading syndrome
+// words, 2^b each).
 struct LdsLayout {
-    uint32_t yhat, s0, ikey, col0, lcol, wsum, foff, fa, fb, fcost, flead, lkey, ls0, words;
+    uint32_t yhat, s0, ikey, col0, lcol, wsum, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
+        ls0, words;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uint32_t low_bits)
@@ -99,6 +102,9 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.fb = o;    o += block;
     L.fcost = o; o += block;
     L.flead = o; o += block;
+    L.fown = o;  o += block;
+    L.iidx = o;  o += ni / 2 + 2;
+    L.lidx = o;  o += (1u << low_bits) / 2 + 2;
     o = (o + 1) & ~1u;          // 8-byte alignment of the table
     L.lkey = o;  o += 1u << low_bits;
     L.ls0 = o;   o += (1u << low_bits) + 8;   // padded for 8-wide reads

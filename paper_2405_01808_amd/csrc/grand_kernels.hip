@@ -77,6 +77,9 @@ struct Arr {
     uint32_t *fb;      // first rank / low index of each slot
     uint32_t *fcost;   // cost of each slot's node
     uint32_t *flead;   // leading syndrome word of each slot's node
+    uint32_t *fown;    // slot that owns the first entry of each thread's run
+    uint32_t *iidx;    // bucket index of the ranked flips
+    uint32_t *lidx;    // bucket index of the low table
 };
 
 // Node store in the workgroup's HBM slot (structure of arrays).
@@ -105,21 +108,14 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t *wsum, uint32_t *total)
     if (lane == 63)
         wsum[wid] = x;
     __syncthreads();
-    if (wid == 0) {
-        uint32_t s = lane < nw ? wsum[lane] : 0u;
-#pragma unroll
-        for (int d = 1; d < 16; d <<= 1) {
-            uint32_t y = __shfl_up(s, d, 64);
-            if (lane >= (uint32_t)d)
-                s += y;
-        }
-        if (lane < nw)
-            wsum[lane] = s;
+    uint32_t base = 0, tot = 0;
+    for (uint32_t w = 0; w < nw; w++) {
+        const uint32_t sw = wsum[w];
+        base += w < wid ? sw : 0u;
+        tot += sw;
     }
-    __syncthreads();
-    uint32_t base = wid ? wsum[wid - 1] : 0u;
-    *total = wsum[nw - 1];
-    __syncthreads();
+    *total = tot;
+    __syncthreads();   // wsum is reused by the next scan
     return base + x - v;
 }
 
@@ -171,44 +167,59 @@ __device__ void rank_sort(uint32_t *a, uint32_t n)
     __syncthreads();
 }
 
-// First index in [lo, hi) whose item cost exceeds x (item costs ascending).
-__device__ inline uint32_t ub_item(const uint32_t *ikey, uint32_t lo, uint32_t hi, int64_t x)
-{
-    if (x < 0)
-        return lo;
-    if (x >= (1ll << 22))
-        return hi;
-    uint32_t key = ((uint32_t)x << 10) | 1023u;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (ikey[mid] > key)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
 // Low-table keys: cost << 13 | mask (cost < 2^19 for b <= 13 flips).
 constexpr uint32_t kMaskBits = 13;
 constexpr uint32_t kMaskAll = (1u << kMaskBits) - 1;
 
-// First index in [lo, hi) of the sorted low table whose cost exceeds x.
-__device__ inline uint32_t ub_low(const uint32_t *lkey, uint32_t lo, uint32_t hi, int64_t x)
+// Bucket index over keys sorted by cost (cost = key >> kshift): idx[u] is
+// the first position whose cost >> shift is at least u, for u in [0, nb].
+// A search for "first cost above x" then scans only x's bucket.
+struct Buckets {
+    const uint32_t *idx;
+    uint32_t shift, nb;
+};
+
+__device__ inline uint32_t bucket_shift(uint32_t cmax, uint32_t nb)
+{
+    uint32_t s = 0;
+    while ((cmax >> s) >= nb)
+        s++;
+    return s;
+}
+
+__device__ void build_buckets(const uint32_t *keys, uint32_t cnt, uint32_t kshift, uint32_t shift,
+                              uint32_t nb, uint32_t *idx)
+{
+    for (uint32_t i = threadIdx.x; i <= cnt; i += blockDim.x) {
+        const uint32_t u0 = i == 0 ? 0u : ((keys[i - 1] >> kshift) >> shift) + 1;
+        const uint32_t u1 = i == cnt ? nb : min((keys[i] >> kshift) >> shift, nb);
+        for (uint32_t u = u0; u <= u1; u++)
+            idx[u] = i;
+    }
+}
+
+// First index in [lo, hi) whose cost exceeds x (keys sorted by cost; x
+// below xlim, the bound that keeps x << kshift within 32 bits).
+__device__ inline uint32_t ub_bucket(const uint32_t *keys, Buckets bk, uint32_t kshift,
+                                     int64_t xlim, uint32_t lo, uint32_t hi, int64_t x)
 {
     if (x < 0)
         return lo;
-    if (x >= (1ll << 19))
+    if (x >= xlim)
         return hi;
-    uint32_t key = ((uint32_t)x << kMaskBits) | kMaskAll;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (lkey[mid] > key)
-            hi = mid;
+    const uint64_t u = (uint64_t)x >> bk.shift;
+    if (u >= bk.nb)
+        return hi;
+    uint32_t a = max(lo, bk.idx[u]), b = min(hi, bk.idx[u + 1]);
+    const uint32_t key = ((uint32_t)x << kshift) | ((1u << kshift) - 1u);
+    while (a < b) {
+        uint32_t mid = (a + b) >> 1;
+        if (keys[mid] > key)
+            b = mid;
         else
-            lo = mid + 1;
+            a = mid + 1;
     }
-    return lo;
+    return min(a, hi);
 }
 
 // Colex comparison of two high subsets given as nodes of the forest (each
@@ -287,11 +298,11 @@ __device__ inline int64_t thr_full(int64_t C, uint32_t n) { return C * (int64_t)
 // Exclusive end of the child ranks r in [rl, n) whose child (cost cp + c_r,
 // maxrank r) threshold k admits.  Costs ascend with r, so the admitted
 // ranks are [rl, end).
-__device__ inline uint32_t child_end(const uint32_t *ikey, uint32_t rl, uint32_t n, Thr k,
-                                     int32_t cp)
+__device__ inline uint32_t child_end(const uint32_t *ikey, Buckets ib, uint32_t rl, uint32_t n,
+                                     Thr k, int32_t cp)
 {
-    uint32_t A = ub_item(ikey, rl, n, (int64_t)k.C - 1 - cp);
-    uint32_t B = ub_item(ikey, A, n, (int64_t)k.C - cp);
+    uint32_t A = ub_bucket(ikey, ib, 10, 1ll << 22, rl, n, (int64_t)k.C - 1 - cp);
+    uint32_t B = ub_bucket(ikey, ib, 10, 1ll << 22, A, n, (int64_t)k.C - cp);
     uint32_t x = min(B, (uint32_t)max(k.R, 0));
     return max(A, x);
 }
@@ -300,14 +311,14 @@ __device__ inline uint32_t child_end(const uint32_t *ikey, uint32_t rl, uint32_t
 // cost_h + LC < C, plus the run with cost_h + LC == C when the pattern's
 // maxrank is below R (the node's own rank, or for the empty high subset the
 // highest bit of the low mask; within a run masks ascend).
-__device__ inline uint32_t node_end(const uint32_t *lkey, uint32_t LB, Thr k, int32_t ch,
-                                    uint32_t h, uint32_t rl, uint32_t ptr)
+__device__ inline uint32_t node_end(const uint32_t *lkey, Buckets lb, uint32_t LB, Thr k,
+                                    int32_t ch, uint32_t h, uint32_t rl, uint32_t ptr)
 {
     // entries before ptr are already checked, and the end never moves back
     if (ptr >= LB || (int64_t)ch + (lkey[ptr] >> kMaskBits) > (int64_t)k.C)
         return ptr;
-    uint32_t a = ub_low(lkey, ptr, LB, (int64_t)k.C - 1 - ch);
-    uint32_t b = ub_low(lkey, a, LB, (int64_t)k.C - ch);
+    uint32_t a = ub_bucket(lkey, lb, kMaskBits, 1ll << 19, ptr, LB, (int64_t)k.C - 1 - ch);
+    uint32_t b = ub_bucket(lkey, lb, kMaskBits, 1ll << 19, a, LB, (int64_t)k.C - ch);
     if (b == a)
         return a;
     if (h != 0)
@@ -355,8 +366,8 @@ __device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t lo, uint32_
 // overflow, the step is rolled back and the threshold gap halved.  Returns
 // the threshold reached (vE when even vE + 1 does not fit; sh.overflow is
 // then set).
-__device__ int64_t expand_nodes(Shared &sh, const Arr &A, const Nodes &nd, uint32_t n,
-                                uint32_t node_cap,
+__device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &nd,
+                                uint32_t n, uint32_t node_cap,
                                 int64_t vE, int64_t vwant)
 {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
@@ -371,18 +382,18 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, const Nodes &nd, uint3
         while (ok && pstart < pend) {
             const uint32_t created_from = sh.used;
             for (uint32_t c0 = pstart; c0 < pend; c0 += bs) {
-                uint32_t h = c0 + tid, cnt = 0, lo = 0, ch = 0, lead = 0;
+                const uint32_t h = c0 + tid;
+                uint32_t cnt = 0, lo = 0, ch = 0, lead = 0;
                 if (h < pend) {
                     ch = nd.cost[h];
                     lo = first ? nd.cnext[h] : nd.rl[h];
                     if (lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
                         lead = nd.lead[h];
-                        uint32_t hi = child_end(A.ikey, lo, n, kn, (int32_t)ch);
-                        cnt = hi - lo;
+                        cnt = child_end(A.ikey, ibk, lo, n, kn, (int32_t)ch) - lo;
                     }
                 }
                 uint32_t total;
-                uint32_t off = block_exscan(cnt, A.wsum, &total);
+                const uint32_t off = block_exscan(cnt, A.wsum, &total);
                 if (sh.used + total > node_cap) {
                     ok = false;   // uniform: every thread sees the same values
                     break;
@@ -425,7 +436,7 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, const Nodes &nd, uint3
         if (tid == 0)
             sh.used = used0;
         for (uint32_t h = tid; h < used0; h += bs)
-            nd.cnext[h] = (uint16_t)child_end(A.ikey, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
+            nd.cnext[h] = (uint16_t)child_end(A.ikey, ibk, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
         __syncthreads();
         if (vn - vE <= 1) {
             if (tid == 0)
@@ -563,6 +574,9 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
             }
         }
     }
+    const uint32_t nbi = max(NI >> 1, 1u);
+    const Buckets ibk{A.iidx, bucket_shift(n ? A.ikey[n - 1] >> 10 : 0u, nbi), nbi};
+    build_buckets(A.ikey, n, 10, ibk.shift, nbi, A.iidx);
     // leading words of every rank's column, full columns of the low flips
     for (uint32_t r = tid; r < n; r += bs)
         A.col0[r] = code.h_cols[(uint64_t)(A.ikey[r] & 1023u) * kw];
@@ -615,6 +629,9 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
             acc ^= A.col0[__builtin_ctz(msk)];
         ls0[i] = acc;
     }
+    const uint32_t nbl = max(LB >> 1, 1u);
+    const Buckets lbk{A.lidx, bucket_shift(lkey[LB - 1] >> kMaskBits, nbl), nbl};
+    build_buckets(lkey, LB, kMaskBits, lbk.shift, nbl, A.lidx);
     // node 0: the empty high subset
     if (tid == 0) {
         nd.cost[0] = 0;
@@ -664,7 +681,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
         vt = min(vt, vmax);
         vt = max(vt, vprev + 1);
         if (vt > vE) {
-            vt = expand_nodes(sh, A, nd, n, a.node_cap, vE, vt);
+            vt = expand_nodes(sh, A, ibk, nd, n, a.node_cap, vE, vt);
             vE = max(vE, vt);
         }
         if (vt <= vprev)      // the store cannot grow any further
@@ -677,33 +694,53 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
         LaneHit best{0xFFFFFFFFu, kNone, 0};
         uint64_t band_size = 0;
         const uint32_t used = sh.used;
+        // the node fields of this thread's slot in the next block are
+        // loaded while the current block is processed
+        uint32_t nx_ptr = 0, nx_cost = 0, nx_lead = 0, nx_rl = 0;
+        if (tid < used) {
+            nx_ptr = nd.ptr[tid];
+            nx_cost = nd.cost[tid];
+            nx_lead = nd.lead[tid];
+            nx_rl = nd.rl[tid];
+        }
         for (uint32_t c0 = 0; c0 < used; c0 += bs) {
-            uint32_t h = c0 + tid, cnt = 0, lo = 0, ch = 0, lead = 0;
+            const uint32_t h = c0 + tid;
+            uint32_t lo = nx_ptr, ch = nx_cost, lead = nx_lead, cnt = 0;
+            const uint32_t rl = nx_rl;
+            if (h + bs < used) {
+                nx_ptr = nd.ptr[h + bs];
+                nx_cost = nd.cost[h + bs];
+                nx_lead = nd.lead[h + bs];
+                nx_rl = nd.rl[h + bs];
+            }
             if (h < used) {
-                lo = nd.ptr[h];
-                ch = nd.cost[h];
-                lead = nd.lead[h];
-                uint32_t hi = node_end(lkey, LB, kt, (int32_t)ch, h, nd.rl[h], lo);
+                uint32_t hi = node_end(lkey, lbk, LB, kt, (int32_t)ch, h, rl, lo);
                 if (hi > lo) {
                     cnt = hi - lo;
                     nd.ptr[h] = (uint16_t)hi;
                 }
             }
-            uint32_t total;
-            uint32_t off = block_exscan(cnt, A.wsum, &total);
-            A.foff[tid] = off;
             A.fa[tid] = h;
             A.fb[tid] = lo;
             A.fcost[tid] = ch;
             A.flead[tid] = lead;
+            uint32_t total;
+            const uint32_t off = block_exscan(cnt, A.wsum, &total);
+            // runs of `run` entries, one per thread; the slot holding a
+            // run's first entry records itself as that run's owner
+            const uint32_t run = (total + bs - 1) / bs;
+            A.foff[tid] = off;
+            if (cnt) {
+                for (uint32_t t = (off + run - 1) / run; t * run < off + cnt; t++)
+                    A.fown[t] = tid;
+            }
             __syncthreads();
             band_size += total;
             const uint32_t ncnt = min(bs, used - c0);
-            const uint32_t run = (total + bs - 1) / bs;
             uint32_t j = tid * run;
             const uint32_t jend = min(total, j + run);
             if (j < jend) {
-                uint32_t k = flat_owner(A.foff, 0, ncnt, j);
+                uint32_t k = A.fown[tid];
                 while (j < jend) {
                     const uint32_t kend = k + 1 < ncnt ? A.foff[k + 1] : total;
                     const uint32_t e = min(jend, kend);
@@ -787,8 +824,8 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
                 int32_t ch = (int32_t)nd.cost[h];
                 if (ch > (int32_t)hc)
                     continue;
-                uint32_t lo = ub_low(lkey, 0, LB, (int64_t)hc - 1 - ch);
-                uint32_t hi = ub_low(lkey, lo, LB, (int64_t)hc - ch);
+                uint32_t lo = ub_bucket(lkey, lbk, kMaskBits, 1ll << 19, 0, LB, (int64_t)hc - 1 - ch);
+                uint32_t hi = ub_bucket(lkey, lbk, kMaskBits, 1ll << 19, lo, LB, (int64_t)hc - ch);
                 below += lo;
                 if (hi > lo) {
                     int c = colex_cmp(nd, h, hit_h);
@@ -886,6 +923,9 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
     w.A.fb = dyn + ly.fb;
     w.A.fcost = dyn + ly.fcost;
     w.A.flead = dyn + ly.flead;
+    w.A.fown = dyn + ly.fown;
+    w.A.iidx = dyn + ly.iidx;
+    w.A.lidx = dyn + ly.lidx;
     w.lkey = dyn + ly.lkey;
     w.ls0 = dyn + ly.ls0;
     const NodeLayout lay = node_layout(a.node_cap);
@@ -899,7 +939,9 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
     return w;
 }
 
-__global__ __launch_bounds__(256) void grand_decode_kernel(KernelArgs a)
+// At most 72 VGPRs (7 waves per SIMD): the kernel is bound by LDS and
+// memory latency, so more resident waves beat the few registers spilled.
+__global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
 {
     __shared__ Shared sh;
     extern __shared__ uint32_t dyn[];
