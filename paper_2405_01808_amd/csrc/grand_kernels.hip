@@ -64,6 +64,23 @@ struct Shared {
     unsigned long long acc;
 };
 
+// Per-slot staging of one block of nodes (one slot per thread).
+struct Stage {
+    uint32_t *foff;    // flat offsets of the slots' ranges
+    uint32_t *fa;      // node of each slot
+    uint32_t *fb;      // first rank / low index of each slot
+    uint32_t *fcost;   // cost of each slot's node
+    uint32_t *flead;   // leading syndrome word of each slot's node
+    uint32_t *fown;    // slot that owns the first entry of each thread's run
+};
+
+// Set `par` (0 or 1) of a staging area whose sets are `stride` words apart.
+__device__ inline Stage stage_set(const Stage &b, uint32_t par, uint32_t stride)
+{
+    const uint32_t o = par * stride;
+    return Stage{b.foff + o, b.fa + o, b.fb + o, b.fcost + o, b.flead + o, b.fown + o};
+}
+
 // Per-workgroup arrays in dynamic LDS, sized for the launch (lds_layout).
 struct Arr {
     uint32_t *yhat;    // hard word, 32-bit words
@@ -72,12 +89,7 @@ struct Arr {
     uint32_t *col0;    // leading syndrome word of each rank's column
     uint32_t *lcol;    // full columns of the low flips
     uint32_t *wsum;    // scan partials, one per wave
-    uint32_t *foff;    // flat offsets of a block of nodes
-    uint32_t *fa;      // node of each slot
-    uint32_t *fb;      // first rank / low index of each slot
-    uint32_t *fcost;   // cost of each slot's node
-    uint32_t *flead;   // leading syndrome word of each slot's node
-    uint32_t *fown;    // slot that owns the first entry of each thread's run
+    Stage st;          // staging: set p of a block starts at offset p * blockDim
     uint32_t *iidx;    // bucket index of the ranked flips
     uint32_t *lidx;    // bucket index of the low table
 };
@@ -95,6 +107,7 @@ struct Nodes {
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
 
 // Exclusive block-wide prefix sum of v; *total receives the sum.
+// Callers keep at least one barrier between two scans (wsum is reused).
 __device__ uint32_t block_exscan(uint32_t v, uint32_t *wsum, uint32_t *total)
 {
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -115,7 +128,6 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t *wsum, uint32_t *total)
         tot += sw;
     }
     *total = tot;
-    __syncthreads();   // wsum is reused by the next scan
     return base + x - v;
 }
 
@@ -377,11 +389,13 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nod
     for (;;) {
         const Thr kn = thr_of(vn, n);
         bool ok = true;
-        uint32_t pstart = 0, pend = used0;
+        uint32_t pstart = 0, pend = used0, used = used0, par = 0;
         bool first = true;
         while (ok && pstart < pend) {
-            const uint32_t created_from = sh.used;
+            const uint32_t created_from = used;
             for (uint32_t c0 = pstart; c0 < pend; c0 += bs) {
+                const Stage S = stage_set(A.st, par, bs);
+                par ^= 1u;
                 const uint32_t h = c0 + tid;
                 uint32_t cnt = 0, lo = 0, ch = 0, lead = 0;
                 if (h < pend) {
@@ -392,49 +406,49 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nod
                         cnt = child_end(A.ikey, ibk, lo, n, kn, (int32_t)ch) - lo;
                     }
                 }
+                S.fa[tid] = h;
+                S.fb[tid] = lo;
+                S.fcost[tid] = ch;
+                S.flead[tid] = lead;
                 uint32_t total;
                 const uint32_t off = block_exscan(cnt, A.wsum, &total);
-                if (sh.used + total > node_cap) {
+                if (used + total > node_cap) {
                     ok = false;   // uniform: every thread sees the same values
                     break;
                 }
-                A.foff[tid] = off;
-                A.fa[tid] = h;
-                A.fb[tid] = lo;
-                A.fcost[tid] = ch;
-                A.flead[tid] = lead;
+                S.foff[tid] = off;
                 if (h < pend && (cnt || !first))
                     nd.cnext[h] = (uint16_t)(lo + cnt);
                 __syncthreads();
                 const uint32_t ncnt = min(bs, pend - c0);
-                const uint32_t dst0 = sh.used;
                 uint32_t k = 0;
                 for (uint32_t j = tid; j < total; j += bs) {
-                    k = flat_owner(A.foff, k, ncnt, j);
-                    uint32_t r = A.fb[k] + (j - A.foff[k]);
-                    uint32_t dst = dst0 + j;
-                    nd.cost[dst] = A.fcost[k] + (A.ikey[r] >> 10);
-                    nd.lead[dst] = A.flead[k] ^ A.col0[r];
-                    nd.par[dst] = A.fa[k];
+                    k = flat_owner(S.foff, k, ncnt, j);
+                    uint32_t r = S.fb[k] + (j - S.foff[k]);
+                    uint32_t dst = used + j;
+                    nd.cost[dst] = S.fcost[k] + (A.ikey[r] >> 10);
+                    nd.lead[dst] = S.flead[k] ^ A.col0[r];
+                    nd.par[dst] = S.fa[k];
                     nd.rl[dst] = (uint16_t)(r + 1);
                     nd.ptr[dst] = 0;
                     nd.cnext[dst] = (uint16_t)(r + 1);
                 }
-                __syncthreads();
-                if (tid == 0)
-                    sh.used = dst0 + total;
-                __syncthreads();
+                used += total;
             }
+            // the next pass reads this pass's children as parents
+            __syncthreads();
             pstart = created_from;
-            pend = sh.used;
+            pend = used;
             first = false;
         }
-        if (ok)
+        if (ok) {
+            if (tid == 0)
+                sh.used = used;
+            __syncthreads();
             return vn;
+        }
         // roll back: drop the new nodes and restore the old child frontiers
         __syncthreads();
-        if (tid == 0)
-            sh.used = used0;
         for (uint32_t h = tid; h < used0; h += bs)
             nd.cnext[h] = (uint16_t)child_end(A.ikey, ibk, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
         __syncthreads();
@@ -464,7 +478,7 @@ __device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t 
 }
 
 __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
-                           uint32_t *ls0, const Nodes &nd, uint32_t jid)
+                           uint32_t *ltmp, uint32_t *ls0, const Nodes &nd, uint32_t jid)
 {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const DevJob job = a.jobs[jid];
@@ -589,39 +603,38 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
     __syncthreads();
 
     // ---- low table: merge A = subsets of flips < j with A + flip j -------
-    for (uint32_t j = 0; j < b; j++) {
-        const uint32_t len = 1u << j, outn = 2 * len;
-        const uint32_t add = ((A.ikey[j] >> 10) << kMaskBits) | (1u << j);
-        const uint32_t per = (outn + bs - 1) / bs;   // <= kMergePer (checked on the host)
-        const uint32_t i0 = min(outn, tid * per), i1 = min(outn, i0 + per);
-        uint32_t out[kMergePer];
-        if (i0 < i1) {
-            // co-rank: number of A entries among the first i0 outputs
-            uint32_t lo = i0 > len ? i0 - len : 0, hi = min(i0, len);
-            while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (lkey[mid] < lkey[i0 - mid - 1] + add)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            uint32_t ia = lo, ib = i0 - lo;
-#pragma unroll
-            for (uint32_t k = 0; k < kMergePer; k++) {
-                if (k < i1 - i0) {
-                    bool takeA = ib >= len || (ia < len && lkey[ia] < lkey[ib] + add);
-                    out[k] = takeA ? lkey[ia] : lkey[ib] + add;
+    // (levels alternate between two buffers: one barrier per level)
+    {
+        uint32_t *src = lkey, *dst = ltmp;
+        for (uint32_t j = 0; j < b; j++) {
+            const uint32_t len = 1u << j, outn = 2 * len;
+            const uint32_t add = ((A.ikey[j] >> 10) << kMaskBits) | (1u << j);
+            const uint32_t per = (outn + bs - 1) / bs;   // <= kMergePer (checked on the host)
+            const uint32_t i0 = min(outn, tid * per), i1 = min(outn, i0 + per);
+            if (i0 < i1) {
+                // co-rank: number of A entries among the first i0 outputs
+                uint32_t lo = i0 > len ? i0 - len : 0, hi = min(i0, len);
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (src[mid] < src[i0 - mid - 1] + add)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                uint32_t ia = lo, ib = i0 - lo;
+                for (uint32_t o = i0; o < i1; o++) {
+                    bool takeA = ib >= len || (ia < len && src[ia] < src[ib] + add);
+                    dst[o] = takeA ? src[ia] : src[ib] + add;
                     ia += takeA;
                     ib += !takeA;
                 }
             }
+            __syncthreads();
+            uint32_t *t = src;
+            src = dst;
+            dst = t;
         }
-        __syncthreads();
-#pragma unroll
-        for (uint32_t k = 0; k < kMergePer; k++)
-            if (i0 + k < i1)
-                lkey[i0 + k] = out[k];
-        __syncthreads();
+        lkey = src;
     }
     for (uint32_t i = tid; i < LB; i += bs) {
         uint32_t acc = 0;
@@ -703,7 +716,10 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
             nx_lead = nd.lead[tid];
             nx_rl = nd.rl[tid];
         }
+        uint32_t par = 0;
         for (uint32_t c0 = 0; c0 < used; c0 += bs) {
+            const Stage S = stage_set(A.st, par, bs);
+            par ^= 1u;
             const uint32_t h = c0 + tid;
             uint32_t lo = nx_ptr, ch = nx_cost, lead = nx_lead, cnt = 0;
             const uint32_t rl = nx_rl;
@@ -720,19 +736,19 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
                     nd.ptr[h] = (uint16_t)hi;
                 }
             }
-            A.fa[tid] = h;
-            A.fb[tid] = lo;
-            A.fcost[tid] = ch;
-            A.flead[tid] = lead;
+            S.fa[tid] = h;
+            S.fb[tid] = lo;
+            S.fcost[tid] = ch;
+            S.flead[tid] = lead;
             uint32_t total;
             const uint32_t off = block_exscan(cnt, A.wsum, &total);
             // runs of `run` entries, one per thread; the slot holding a
             // run's first entry records itself as that run's owner
             const uint32_t run = (total + bs - 1) / bs;
-            A.foff[tid] = off;
+            S.foff[tid] = off;
             if (cnt) {
                 for (uint32_t t = (off + run - 1) / run; t * run < off + cnt; t++)
-                    A.fown[t] = tid;
+                    S.fown[t] = tid;
             }
             __syncthreads();
             band_size += total;
@@ -740,13 +756,13 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
             uint32_t j = tid * run;
             const uint32_t jend = min(total, j + run);
             if (j < jend) {
-                uint32_t k = A.fown[tid];
+                uint32_t k = S.fown[tid];
                 while (j < jend) {
-                    const uint32_t kend = k + 1 < ncnt ? A.foff[k + 1] : total;
+                    const uint32_t kend = k + 1 < ncnt ? S.foff[k + 1] : total;
                     const uint32_t e = min(jend, kend);
-                    const uint32_t l0 = A.fb[k] + (j - A.foff[k]);
+                    const uint32_t l0 = S.fb[k] + (j - S.foff[k]);
                     const uint32_t cntk = e - j;
-                    const uint32_t ld = A.flead[k];
+                    const uint32_t ld = S.flead[k];
                     // min over (entry XOR lead) is zero iff a leading word
                     // matches; reading up to 7 entries past the piece (the
                     // table is padded) can only cause a spurious rescan below
@@ -758,18 +774,19 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
                     }
                     const bool any = mn == 0;
                     if (any) {   // a leading word matched: verify and keep the best
-                        const uint32_t node = A.fa[k], nc = A.fcost[k];
+                        const uint32_t node = S.fa[k], nc = S.fcost[k];
                         for (uint32_t t = 0; t < cntk; t++)
                             if (ls0[l0 + t] == ld && full_zero(A, nd, code, lkey, node, l0 + t))
                                 keep_best(best, nd, lkey, nc + (lkey[l0 + t] >> kMaskBits), node,
                                           l0 + t);
                     }
                     j = e;
-                    while (k + 1 < ncnt && A.foff[k + 1] <= j)
+                    while (k + 1 < ncnt && S.foff[k + 1] <= j)
                         k++;
                 }
             }
-            __syncthreads();
+            // no barrier: the next block stages into the other set, and its
+            // scan barrier keeps the block after it from reusing this one
         }
 
         // best hit of the band across the workgroup
@@ -904,7 +921,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
 
 struct Workspace {
     Arr A;
-    uint32_t *lkey, *ls0;
+    uint32_t *lkey, *ltmp, *ls0;
     Nodes nd;
 };
 
@@ -918,15 +935,12 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
     w.A.col0 = dyn + ly.col0;
     w.A.lcol = dyn + ly.lcol;
     w.A.wsum = dyn + ly.wsum;
-    w.A.foff = dyn + ly.foff;
-    w.A.fa = dyn + ly.fa;
-    w.A.fb = dyn + ly.fb;
-    w.A.fcost = dyn + ly.fcost;
-    w.A.flead = dyn + ly.flead;
-    w.A.fown = dyn + ly.fown;
+    w.A.st = Stage{dyn + ly.foff, dyn + ly.fa, dyn + ly.fb, dyn + ly.fcost, dyn + ly.flead,
+                   dyn + ly.fown};
     w.A.iidx = dyn + ly.iidx;
     w.A.lidx = dyn + ly.lidx;
     w.lkey = dyn + ly.lkey;
+    w.ltmp = dyn + ly.ltmp;
     w.ls0 = dyn + ly.ls0;
     const NodeLayout lay = node_layout(a.node_cap);
     uint8_t *slot = a.scratch + (uint64_t)blockIdx.x * lay.total;
@@ -954,7 +968,7 @@ __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
         __syncthreads();
         if (jid >= a.njobs)
             break;
-        decode_one(a, sh, w.A, w.lkey, w.ls0, w.nd, jid);
+        decode_one(a, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, jid);
         __syncthreads();
     }
 }
@@ -1034,7 +1048,7 @@ __global__ __launch_bounds__(256) void grand_serve_kernel(ServeArgs s)
         if (state == kSkip)
             continue;
         const uint32_t slot = (uint32_t)(idx % s.ring);
-        decode_one(s.base, sh, w.A, w.lkey, w.ls0, w.nd, slot);
+        decode_one(s.base, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, slot);
         // every thread publishes its own result stores before the flag
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
         __syncthreads();
