@@ -164,27 +164,27 @@ int grand_tuning_set(uint32_t n, uint32_t M, const grand_tuning *t);
 /* ------------------------------------------------------------------ */
 
 /* A server admits requests (Algorithm 2 decodes, one codeword each) as they
- * arrive, within a slot count and a device-memory budget.  Two modes:
- *   GRAND_SERVE_LANES      several HIP streams ("lanes"): whenever a lane is
- *                          free, every admitted request not yet on the device
- *                          is staged and launched on it as one batch, so
- *                          batches launched at different times overlap;
- *   GRAND_SERVE_PERSISTENT one resident kernel whose workgroups pull
- *                          requests one by one from a ring in coherent pinned
- *                          memory as the host publishes them.  Currently
- *                          DISABLED: grand_server_create returns GRAND_EINVAL
- *                          for it.
- * A request's result is bit-identical to grand_decode of the same input,
- * whatever else is in flight.  Server calls are serialised internally and
- * may come from several host threads. */
+ * arrive, within a slot count and a device-memory budget, and keeps several
+ * HIP streams ("lanes") busy.  Whenever a lane is free, every admitted
+ * request not yet on the device (up to max_batch) is written into the lane's
+ * coherent pinned buffers and decoded as one launch, heaviest first.  The
+ * kernel reads the requests in place and writes each result back with a
+ * completion flag, so grand_server_poll returns a request as soon as its own
+ * decode has ended, not when its launch has.  Launches on different lanes
+ * overlap on the device while new requests keep being admitted.  A request's
+ * result is bit-identical to grand_decode of the same input, whatever else
+ * is in flight.  Server calls are serialised internally and may come from
+ * several host threads.
+ *   GRAND_SERVE_LANES      the mode described above (the only one available);
+ *   GRAND_SERVE_PERSISTENT reserved: grand_server_create returns GRAND_EINVAL. */
 enum { GRAND_SERVE_LANES = 0, GRAND_SERVE_PERSISTENT = 1 };
 typedef struct grand_server grand_server;
 
 typedef struct {
-    uint32_t max_inflight;     /* admitted, not yet returned requests (1..2^20);
-                                  also the ring size in persistent mode */
-    uint32_t lanes;            /* lanes mode: streams used concurrently (1..8) */
-    uint32_t max_batch;        /* lanes mode: requests per launch (1..65536) */
+    uint32_t max_inflight;     /* admitted, not yet returned requests (1..2^20) */
+    uint32_t lanes;            /* streams used concurrently (1..32); HIP maps them
+                                  onto GPU_MAX_HW_QUEUES hardware queues */
+    uint32_t max_batch;        /* requests per launch (1..65536) */
     uint32_t mode;             /* GRAND_SERVE_LANES or GRAND_SERVE_PERSISTENT */
     uint64_t memory_budget;    /* device bytes reserved for admitted requests;
                                   each reserves grand_request_bytes(n, M) */

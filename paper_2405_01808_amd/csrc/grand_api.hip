@@ -154,8 +154,9 @@ int ensure_pinned(T **p, size_t *cap, size_t want)
 int init_stream_res(StreamRes &r)
 {
     if (!r.queues) {
-        if (hipMalloc((void **)&r.queues, 64 * sizeof(uint32_t)) != hipSuccess)
+        if (hipMalloc((void **)&r.queues, 64 * sizeof(unsigned long long)) != hipSuccess)
             return fail(GRAND_ENOMEM, "hipMalloc failed for work counters");
+        HIP_TRY(hipMemset(r.queues, 0, 64 * sizeof(unsigned long long)));
         HIP_TRY(hipEventCreateWithFlags(&r.staged, hipEventDisableTiming));
         if (hipMalloc((void **)&r.d_rx, 2 * kMaxItems * sizeof(float)) != hipSuccess ||
             hipMalloc((void **)&r.d_out, (kCwStride + 2) * sizeof(uint64_t)) != hipSuccess ||
@@ -244,12 +245,15 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
         a.status_out = status_out;
         a.checks_out = checks_out;
         a.queue = r.queues + (i % 64);
+        a.qbase = r.qnext[i % 64];
         a.scratch = r.scratch;
-        if (launch_reset(a.queue, stream))
-            return fail(GRAND_EDEVICE, "reset kernel launch failed");
+        a.done_out = nullptr;
+        a.done_seq = 0;
+        a.pad2 = 0;
         if (launch_decode(a, grids[i], t.block, stream))
             return fail(GRAND_EDEVICE, std::string("decode kernel launch failed: ") +
                                            hipGetErrorString(hipGetLastError()));
+        r.qnext[i % 64] += a.njobs + grids[i];
     }
     return GRAND_OK;
 }

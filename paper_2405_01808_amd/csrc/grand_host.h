@@ -36,7 +36,8 @@ int fail(int code, const std::string &msg);
 struct StreamRes {
     uint8_t *scratch = nullptr;     // high-subset stores, one slot per workgroup
     size_t scratch_bytes = 0;
-    uint32_t *queues = nullptr;     // 64 work counters
+    unsigned long long *queues = nullptr;   // 64 work counters (never reset)
+    uint64_t qnext[64] = {};        // each counter's value once queued launches end
     DevJob *jobs = nullptr;
     size_t jobs_cap = 0;
     DevCode *codes = nullptr;
@@ -71,6 +72,9 @@ uint32_t symbols(uint32_t n, uint32_t M);
 grand_tuning tuning_for(uint32_t n, uint32_t M);
 int current_ctx(DeviceCtx **out);
 int init_stream_res(StreamRes &r);
+// Grow r's high-subset stores to `bytes` (synchronises the device when an
+// existing buffer has to be replaced).
+int ensure_scratch(StreamRes &r, size_t bytes);
 // mixed: 1 = one launch for all words, 0 = one launch per (n, M) bucket,
 // -1 = one launch when no bucket fills the device on its own.
 int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream,

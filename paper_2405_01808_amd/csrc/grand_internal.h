@@ -50,8 +50,12 @@ struct KernelArgs {
     uint8_t *ab_out;
     int32_t *status_out;  // may be null
     uint64_t *checks_out; // may be null
-    uint32_t *queue;      // work counter, zero at launch
+    unsigned long long *queue;  // work counter; a launch takes indices from qbase on
+    unsigned long long qbase;   // counter value at launch: ends at qbase + njobs + grid
     uint8_t *scratch;     // grid x node_layout(node_cap).total bytes
+    uint32_t *done_out;   // may be null: per-word completion flags (by output slot),
+    uint32_t done_seq;    //   set to done_seq once the word's outputs are visible
+    uint32_t pad2;
 };
 
 // Layout of one workgroup's high-subset store (byte offsets; 18 B/entry).
@@ -127,41 +131,9 @@ inline uint32_t items_pow2(uint32_t n, uint32_t M)
     return p;
 }
 
-// Persistent serving.  The host publishes request i by writing its job,
-// code and received values into ring slot i % ring (coherent pinned memory)
-// and then raising `tail` past i.  Workgroups claim indices in order from a
-// device counter; the one holding the lowest unpublished index polls `tail`
-// over the bus and mirrors it into device memory, the others poll the
-// mirror.  A workgroup decodes its request in place, writes the results into
-// the slot and finally sets done[slot] = i + 1.
-struct ServeCtl {            // coherent pinned memory, written by the host
-    uint64_t tail;           // requests published
-    uint32_t stop;           // nonzero: leave
-    uint32_t pad[13];
-};
-
-struct ServeDev {            // device memory
-    uint64_t head;           // next index to claim
-    uint64_t dtail;          // mirror of tail (never ahead of it)
-    uint32_t quit;           // set by the first workgroup to leave
-    uint32_t pad[11];
-};
-
-struct ServeArgs {
-    KernelArgs base;         // jobs, codes, rx and outputs point into the ring
-    ServeCtl *ctl;
-    uint64_t *done;          // coherent pinned [ring]
-    ServeDev *dev;
-    uint64_t start;          // first index this launch claims
-    uint64_t idle_ticks;     // wall-clock ticks without a publish before leaving
-    uint32_t ring;
-    uint32_t pad;
-};
-
-// Launch the decoder for one group of jobs sharing a tuning.
+// Launch the decoder for one group of jobs sharing a tuning.  Every
+// workgroup takes indices until one is past the batch, so the counter
+// advances by exactly njobs + grid.
 int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stream);
-int launch_reset(uint32_t *queue, void *stream);
-// Reset the serving counters to `start` and launch the serving kernel.
-int launch_serve(const ServeArgs &s, uint32_t grid, uint32_t block, void *stream);
 
 }  // namespace grand

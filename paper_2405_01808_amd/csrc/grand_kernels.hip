@@ -50,8 +50,6 @@ namespace {
 // Per-workgroup scalars (static LDS).
 struct Shared {
     uint32_t job;
-    uint32_t state;                  // serving: kWork, kSkip or kExit
-    unsigned long long sidx;         // serving: claimed request index
     uint32_t nitems;
     uint32_t err;
     uint32_t used;                   // nodes in the store
@@ -477,8 +475,9 @@ __device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t 
     }
 }
 
-__device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
-                           uint32_t *ltmp, uint32_t *ls0, const Nodes &nd, uint32_t jid)
+// Returns the word's output slot.
+__device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
+                               uint32_t *ltmp, uint32_t *ls0, const Nodes &nd, uint32_t jid)
 {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const DevJob job = a.jobs[jid];
@@ -492,7 +491,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
         // metadata the host never produces: fail the word rather than loop
         if (threadIdx.x == 0 && a.status_out)
             a.status_out[job.out] = -1;   // GRAND_EINVAL
-        return;
+        return job.out;
     }
     const int32_t levels = 1 << m;
     const uint32_t L = (n_bits + 2 * m - 1) / (2 * m);
@@ -554,7 +553,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
     if (sh.err) {
         if (tid == 0 && a.status_out)
             a.status_out[out_slot] = -1;   // GRAND_EINVAL
-        return;
+        return out_slot;
     }
     // ---- Step 2: rank the flips --------------------------------------
     if (NI <= 256 && NI <= 2 * bs)
@@ -917,6 +916,7 @@ __device__ void decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32
         if (a.checks_out)
             a.checks_out[out_slot] = checks;
     }
+    return out_slot;
 }
 
 struct Workspace {
@@ -961,116 +961,22 @@ __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
     extern __shared__ uint32_t dyn[];
     const Workspace w = workspace(a, dyn);
     for (;;) {
-        if (threadIdx.x == 0)
-            sh.job = atomicAdd(a.queue, 1u);
+        if (threadIdx.x == 0) {
+            const unsigned long long c = atomicAdd(a.queue, 1ull) - a.qbase;
+            sh.job = c < a.njobs ? (uint32_t)c : kNone;
+        }
         __syncthreads();
         const uint32_t jid = sh.job;
         __syncthreads();
-        if (jid >= a.njobs)
+        if (jid == kNone)
             break;
-        decode_one(a, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, jid);
-        __syncthreads();
-    }
-}
-
-// Persistent serving (the request protocol is described with ServeArgs).
-enum : uint32_t { kWork = 0, kSkip = 1, kExit = 2 };
-
-// Claim the next request index and wait until it is published.  Only the
-// workgroup holding the lowest unpublished index reads the host's counter;
-// it also watches `stop` and the idle limit, and leaving sets `quit` for the
-// whole grid.  A workgroup never leaves while holding a published index, so
-// every index it gives up is unpublished at that time and is claimed again
-// by the next launch.
-__device__ uint32_t serve_claim(const ServeArgs &s, unsigned long long *out_idx)
-{
-    ServeDev *d = s.dev;
-    if (__hip_atomic_load(&d->quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        return kExit;
-    const unsigned long long idx = atomicAdd((unsigned long long *)&d->head, 1ull);
-    *out_idx = idx;
-    bool holder = false;
-    uint64_t since = 0;
-    for (;;) {
-        const uint64_t dt = __hip_atomic_load(&d->dtail, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-        if (dt > idx)
-            break;
-        if (dt == idx) {
-            const uint64_t t = __hip_atomic_load(&s.ctl->tail, __ATOMIC_ACQUIRE,
-                                                 __HIP_MEMORY_SCOPE_SYSTEM);
-            if (t > idx) {
-                atomicMax((unsigned long long *)&d->dtail, (unsigned long long)t);
-                break;
-            }
-            const uint64_t now = wall_clock64();
-            if (!holder) {
-                holder = true;
-                since = now;
-            }
-            if (__hip_atomic_load(&s.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
-                now - since > s.idle_ticks) {
-                __hip_atomic_store(&d->quit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return kExit;
-            }
-            __builtin_amdgcn_s_sleep(4);
-        } else {
-            if (__hip_atomic_load(&d->quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                return kExit;
-            // farther from the front: poll the mirror less often
-            const uint32_t k = (uint32_t)min(idx - dt, 16ull);
-            for (uint32_t i = 0; i < k; i++)
-                __builtin_amdgcn_s_sleep(16);
-        }
-    }
-    // system-scope acquire: the host's writes to the slot are visible below
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-    if (__hip_atomic_load(&s.done[idx % s.ring], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >
-        idx)
-        return kSkip;   // decoded by an earlier launch (slot indices only grow)
-    return kWork;
-}
-
-__global__ __launch_bounds__(256) void grand_serve_kernel(ServeArgs s)
-{
-    __shared__ Shared sh;
-    extern __shared__ uint32_t dyn[];
-    const Workspace w = workspace(s.base, dyn);
-    for (;;) {
-        if (threadIdx.x == 0)
-            sh.state = serve_claim(s, &sh.sidx);
-        __syncthreads();
-        const uint32_t state = sh.state;
-        const uint64_t idx = sh.sidx;
-        __syncthreads();
-        if (state == kExit)
-            break;
-        if (state == kSkip)
-            continue;
-        const uint32_t slot = (uint32_t)(idx % s.ring);
-        decode_one(s.base, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, slot);
-        // every thread publishes its own result stores before the flag
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&s.done[slot], idx + 1, __ATOMIC_RELEASE,
+        const uint32_t out = decode_one(a, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, jid);
+        // thread 0 wrote every output of the word: publish them, then the flag
+        if (a.done_out && threadIdx.x == 0)
+            __hip_atomic_store(&a.done_out[out], a.done_seq, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_SYSTEM);
+        __syncthreads();
     }
-}
-
-__global__ void serve_reset_kernel(ServeDev *d, uint64_t start)
-{
-    if (threadIdx.x == 0) {
-        d->head = start;
-        d->dtail = start;
-        d->quit = 0;
-    }
-}
-
-__global__ void reset_kernel(uint32_t *q)
-{
-    if (threadIdx.x == 0)
-        q[0] = 0;
 }
 
 }  // namespace
@@ -1082,26 +988,6 @@ int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stre
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return -3;
     hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-int launch_serve(const ServeArgs &sa, uint32_t grid, uint32_t block, void *stream)
-{
-    const uint32_t lds = 4u * lds_layout(sa.base.ni, block, sa.base.low_bits).words;
-    if (hipFuncSetAttribute((const void *)grand_serve_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -3;
-    hipLaunchKernelGGL(serve_reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, sa.dev,
-                       sa.start);
-    if (hipGetLastError() != hipSuccess)
-        return -3;
-    hipLaunchKernelGGL(grand_serve_kernel, dim3(grid), dim3(block), lds, (hipStream_t)stream, sa);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-int launch_reset(uint32_t *queue, void *stream)
-{
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, queue);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

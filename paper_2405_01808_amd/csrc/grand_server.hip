@@ -2,19 +2,16 @@
 // real-time replay of recorded arrival streams (server and plain paths).
 //
 // Requests are admitted within a slot count and a device-memory budget.
-//
-// Lanes mode: each lane is one HIP stream with its own staging and device
-// buffers; when a lane is idle, every admitted request not yet launched is
-// copied to it and decoded as one batch (grand_decode_batch's path), so
-// batches launched at different times overlap on the device.  Completion is
-// observed with stream events; results are copied back asynchronously into
-// pinned memory before the event, so harvesting never blocks.
-//
-// Persistent mode: one resident kernel pulls requests from a ring in
-// coherent pinned memory (ServeArgs describes the protocol).  Submitting
-// writes the request into its slot and raises the published count; polling
-// reads the slots' completion flags.  No copy or launch is issued per
-// request; the kernel is relaunched only after it left on an idle period.
+// Each lane is one HIP stream with its own buffers in coherent pinned
+// memory.  When a lane is idle, every admitted request not yet launched is
+// written into its buffers and decoded as one launch, heaviest first; the
+// kernel reads the requests in place and writes each result back together
+// with a per-request completion flag, so a request is returned as soon as
+// its own decode ends, not when its whole launch does.  The lane's stream
+// event still marks the end of the launch (every result is then final), so
+// a flag that is never seen delays a result but cannot lose it.  Launches
+// on different lanes overlap on the device while new requests keep being
+// admitted.
 
 #include <hip/hip_runtime.h>
 
@@ -23,7 +20,6 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <unordered_map>
@@ -53,55 +49,31 @@ struct Request {
     uint64_t bytes;
 };
 
+constexpr uint32_t kSlotFloats = kMaxItems;   // 2L <= N <= 1024 received values
+
 struct Lane {
     hipStream_t stream = nullptr;
-    StreamRes res;
     hipEvent_t done = nullptr;
+    StreamRes res;                    // work counters and high-subset stores
     bool busy = false;
-    uint32_t cap = 0;                 // requests the buffers hold
-    // device
-    float *d_rx = nullptr;
-    uint64_t *d_cw = nullptr, *d_q = nullptr, *d_chk = nullptr;
-    uint8_t *d_ab = nullptr;
-    int32_t *d_st = nullptr;
-    // pinned
-    float *h_rx = nullptr;
-    uint64_t *h_cw = nullptr, *h_q = nullptr, *h_chk = nullptr;
-    uint8_t *h_ab = nullptr;
-    int32_t *h_st = nullptr;
-    std::vector<Request> reqs;        // the batch on the device
+    uint32_t cap = 0;                 // requests per launch
+    uint32_t grid = 0;                // workgroups per launch at most
+    uint32_t seq = 0;                 // launch number, the value of its flags
+    // coherent pinned memory used by the kernel in place (host view; d_*
+    // is the device's view)
+    DevJob *jobs = nullptr, *d_jobs = nullptr;
+    DevCode *codes = nullptr, *d_codes = nullptr;
+    float *rx = nullptr, *d_rx = nullptr;
+    uint64_t *cw = nullptr, *d_cw = nullptr;
+    uint64_t *q = nullptr, *d_q = nullptr;
+    uint64_t *chk = nullptr, *d_chk = nullptr;
+    uint8_t *ab = nullptr, *d_ab = nullptr;
+    int32_t *st = nullptr, *d_st = nullptr;
+    uint32_t *flag = nullptr, *d_flag = nullptr;
+    std::vector<Request> reqs;        // slot i of the launch
+    std::vector<uint8_t> taken;       // slot already returned
+    uint32_t left = 0;                // slots not yet returned
 };
-
-// Persistent-mode state.  Slot i % ring of the coherent pinned arrays holds
-// published request i until it is harvested.
-struct Persist {
-    hipStream_t stream = nullptr;
-    hipEvent_t kdone = nullptr;       // recorded after each launch
-    bool launched = false;
-    uint32_t ring = 0, grid = 0;
-    grand_tuning t{};
-    uint64_t idle_ticks = 0;
-    // coherent pinned (host pointers; d_* are the device's views)
-    ServeCtl *ctl = nullptr;
-    uint64_t *done = nullptr;
-    DevJob *jobs = nullptr;
-    DevCode *codes = nullptr;
-    float *rx = nullptr;
-    uint64_t *cw = nullptr, *q = nullptr, *chk = nullptr;
-    uint8_t *ab = nullptr;
-    int32_t *st = nullptr;
-    ServeArgs args{};                 // device views, fixed at creation
-    // device
-    ServeDev *dev = nullptr;
-    uint8_t *scratch = nullptr;
-    uint32_t *queue = nullptr;        // unused by the serving kernel
-    uint64_t tail = 0;                // published
-    std::vector<uint8_t> busy;        // slot holds a published, unharvested request
-    std::map<uint64_t, Request> live; // published requests by index
-};
-
-constexpr uint32_t kSlotFloats = kMaxItems;   // 2L <= N <= 1024 received values
-constexpr double kIdleSeconds = 0.05;          // kernel leaves after this long idle
 
 }  // namespace
 
@@ -114,53 +86,60 @@ struct grand_server {
     std::deque<grand_result> done;
     uint64_t next_id = 1;
     uint64_t inflight = 0;            // admitted and not yet returned
-    uint64_t running = 0;             // on the device
+    uint64_t running = 0;             // launched and not yet returned
     uint64_t mem_in_use = 0;
-    std::unique_ptr<Persist> pers;    // persistent mode only
 };
 
 namespace {
 
-int lane_init(Lane &L, uint32_t cap)
+template <typename T>
+int coherent_alloc(T **h, size_t count, T **d)
+{
+    if (hipHostMalloc((void **)h, std::max<size_t>(count, 1) * sizeof(T),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        *h = nullptr;
+        return fail(GRAND_ENOMEM, "hipHostMalloc failed for server lane buffers");
+    }
+    std::memset(*h, 0, std::max<size_t>(count, 1) * sizeof(T));
+    HIP_TRY(hipHostGetDevicePointer((void **)d, *h, 0));
+    return GRAND_OK;
+}
+
+int lane_init(Lane &L, uint32_t cap, uint32_t grid)
 {
     HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
     L.cap = cap;
-    const size_t rxf = (size_t)cap * 2 * kMaxItems;
-    if (hipMalloc((void **)&L.d_rx, rxf * sizeof(float)) != hipSuccess ||
-        hipMalloc((void **)&L.d_cw, (size_t)cap * kCwStride * 8) != hipSuccess ||
-        hipMalloc((void **)&L.d_q, (size_t)cap * 8) != hipSuccess ||
-        hipMalloc((void **)&L.d_chk, (size_t)cap * 8) != hipSuccess ||
-        hipMalloc((void **)&L.d_ab, cap) != hipSuccess ||
-        hipMalloc((void **)&L.d_st, (size_t)cap * 4) != hipSuccess)
-        return fail(GRAND_ENOMEM, "hipMalloc failed for server lane buffers");
-    if (hipHostMalloc((void **)&L.h_rx, rxf * sizeof(float), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&L.h_cw, (size_t)cap * kCwStride * 8, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void **)&L.h_q, (size_t)cap * 8, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&L.h_chk, (size_t)cap * 8, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&L.h_ab, cap, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&L.h_st, (size_t)cap * 4, hipHostMallocDefault) != hipSuccess)
-        return fail(GRAND_ENOMEM, "hipHostMalloc failed for server lane buffers");
-    return init_stream_res(L.res);
+    L.grid = grid;
+    int rc;
+    if ((rc = coherent_alloc(&L.jobs, cap, &L.d_jobs)) ||
+        (rc = coherent_alloc(&L.codes, cap, &L.d_codes)) ||
+        (rc = coherent_alloc(&L.rx, (size_t)cap * kSlotFloats, &L.d_rx)) ||
+        (rc = coherent_alloc(&L.cw, (size_t)cap * kCwStride, &L.d_cw)) ||
+        (rc = coherent_alloc(&L.q, cap, &L.d_q)) ||
+        (rc = coherent_alloc(&L.chk, cap, &L.d_chk)) ||
+        (rc = coherent_alloc(&L.ab, cap, &L.d_ab)) ||
+        (rc = coherent_alloc(&L.st, cap, &L.d_st)) ||
+        (rc = coherent_alloc(&L.flag, cap, &L.d_flag)))
+        return rc;
+    if ((rc = init_stream_res(L.res)))
+        return rc;
+    return ensure_scratch(L.res, (size_t)grid * node_layout(tuning_for(0, 0).node_cap).total);
 }
 
 void lane_free(Lane &L)
 {
     if (L.stream)
         (void)hipStreamSynchronize(L.stream);
-    (void)hipFree(L.d_rx);
-    (void)hipFree(L.d_cw);
-    (void)hipFree(L.d_q);
-    (void)hipFree(L.d_chk);
-    (void)hipFree(L.d_ab);
-    (void)hipFree(L.d_st);
-    (void)hipHostFree(L.h_rx);
-    (void)hipHostFree(L.h_cw);
-    (void)hipHostFree(L.h_q);
-    (void)hipHostFree(L.h_chk);
-    (void)hipHostFree(L.h_ab);
-    (void)hipHostFree(L.h_st);
+    (void)hipHostFree(L.jobs);
+    (void)hipHostFree(L.codes);
+    (void)hipHostFree(L.rx);
+    (void)hipHostFree(L.cw);
+    (void)hipHostFree(L.q);
+    (void)hipHostFree(L.chk);
+    (void)hipHostFree(L.ab);
+    (void)hipHostFree(L.st);
+    (void)hipHostFree(L.flag);
     StreamRes &r = L.res;
     (void)hipFree(r.scratch);
     (void)hipFree(r.queues);
@@ -184,273 +163,124 @@ void lane_free(Lane &L)
         (void)hipStreamDestroy(L.stream);
 }
 
-// Move every pending request (up to the lane's capacity) onto an idle lane.
+// Return slot i of a lane's launch.
+void lane_emit(grand_server *s, Lane &L, uint32_t i, double t)
+{
+    const Request &q = L.reqs[i];
+    grand_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.request_id = q.id;
+    r.status = L.st[i];
+    if (r.status == GRAND_OK) {
+        std::memcpy(r.codeword, L.cw + (size_t)i * kCwStride, ((q.code->n + 63) / 64) * 8);
+        r.queries = L.q[i];
+        r.checks = L.chk[i];
+        r.abandoned = L.ab[i];
+    } else {
+        r.abandoned = 1;
+    }
+    r.arrival_s = q.arrival_s;
+    r.submit_s = q.submit_s;
+    r.complete_s = t;
+    s->done.push_back(r);
+    s->mem_in_use -= q.bytes;
+    s->inflight--;
+    s->running--;
+    L.taken[i] = 1;
+    L.left--;
+}
+
+// Move pending requests (up to the lane's capacity) onto an idle lane and
+// launch them, heaviest first.
 int lane_launch(grand_server *s, Lane &L)
 {
     const uint32_t B = (uint32_t)std::min<size_t>(s->pending.size(), L.cap);
     if (B == 0)
         return GRAND_OK;
     L.reqs.clear();
-    std::vector<const grand_code *> codes;
-    std::vector<uint32_t> code_index(B), Mv(B);
-    std::vector<uint64_t> capv(B), offs(B);
-    std::vector<float> nvv(B);
-    std::map<const grand_code *, uint32_t> cidx;
-    uint64_t off = 0;
     for (uint32_t i = 0; i < B; i++) {
-        Request &q = s->pending.front();
-        auto it = cidx.find(q.code);
-        if (it == cidx.end()) {
-            it = cidx.emplace(q.code, (uint32_t)codes.size()).first;
-            codes.push_back(q.code);
-        }
-        code_index[i] = it->second;
-        Mv[i] = q.M;
-        capv[i] = q.cap;
-        nvv[i] = q.noise_var;
-        offs[i] = off;
-        std::memcpy(L.h_rx + off, q.rx.data(), q.rx.size() * sizeof(float));
-        off += q.rx.size();
-        L.reqs.push_back(std::move(q));
+        L.reqs.push_back(std::move(s->pending.front()));
         s->pending.pop_front();
     }
-    HIP_TRY(hipMemcpyAsync(L.d_rx, L.h_rx, off * sizeof(float), hipMemcpyHostToDevice, L.stream));
-    grand_batch b;
-    b.count = B;
-    b.n_codes = (uint32_t)codes.size();
-    b.codes = codes.data();
-    b.code_index = code_index.data();
-    b.M = Mv.data();
-    b.query_cap = capv.data();
-    b.noise_var = nvv.data();
-    b.rx_offset = offs.data();
-    b.rx = L.d_rx;
-    b.codeword_out = L.d_cw;
-    b.queries_out = L.d_q;
-    b.abandoned_out = L.d_ab;
-    b.status_out = L.d_st;
-    b.checks_out = L.d_chk;
-    int rc = decode_batch_on(s->ctx, L.res, &b, L.stream, 1);
-    if (rc) {   // return the batch as failed requests instead of losing it
-        const double t = now_s();
-        for (const Request &q : L.reqs) {
-            grand_result r;
-            std::memset(&r, 0, sizeof(r));
-            r.request_id = q.id;
-            r.status = rc;
-            r.abandoned = 1;
-            r.arrival_s = q.arrival_s;
-            r.submit_s = q.submit_s;
-            r.complete_s = t;
-            s->done.push_back(r);
-            s->mem_in_use -= q.bytes;
-            s->inflight--;
+    std::stable_sort(L.reqs.begin(), L.reqs.end(), [](const Request &x, const Request &y) {
+        const uint32_t wx = items_pow2(x.code->n, x.M), wy = items_pow2(y.code->n, y.M);
+        if (wx != wy)
+            return wx > wy;
+        return x.cap > y.cap;
+    });
+    uint32_t ni = 1;
+    for (uint32_t i = 0; i < B; i++) {
+        const Request &q = L.reqs[i];
+        const grand_code *c = q.code;
+        L.codes[i] = DevCode{c->n, c->rows, c->kw, c->row_w32, c->d_rows, c->d_cols};
+        L.jobs[i] = DevJob{i, q.M, (uint64_t)i * kSlotFloats, q.cap, i, 0};
+        std::memcpy(L.rx + (size_t)i * kSlotFloats, q.rx.data(), q.rx.size() * sizeof(float));
+        ni = std::max(ni, items_pow2(c->n, q.M));
+    }
+    const grand_tuning t = tuning_for(0, 0);
+    const uint32_t grid = std::max(1u, std::min(B, L.grid));
+    L.seq = L.seq + 1 ? L.seq + 1 : 1;   // flags of this launch hold seq (never 0)
+    KernelArgs a;
+    a.codes = L.d_codes;
+    a.jobs = L.d_jobs;
+    a.njobs = B;
+    a.low_bits = t.low_bits;
+    a.first_band = t.first_band;
+    a.band_growth = t.band_growth;
+    a.node_cap = t.node_cap;
+    a.ni = ni;
+    a.rx = L.d_rx;
+    a.cw_out = L.d_cw;
+    a.q_out = L.d_q;
+    a.ab_out = L.d_ab;
+    a.status_out = L.d_st;
+    a.checks_out = L.d_chk;
+    a.queue = L.res.queues;
+    a.qbase = L.res.qnext[0];
+    a.scratch = L.res.scratch;
+    a.done_out = L.d_flag;
+    a.done_seq = L.seq;
+    a.pad2 = 0;
+    L.taken.assign(B, 0);
+    L.left = B;
+    s->running += B;
+    int rc = launch_decode(a, grid, t.block, L.stream) ? GRAND_EDEVICE : GRAND_OK;
+    if (rc == GRAND_OK) {
+        L.res.qnext[0] += B + grid;
+        if (hipEventRecord(L.done, L.stream) != hipSuccess)
+            rc = GRAND_EDEVICE;
+    }
+    if (rc) {   // return the launch as failed requests instead of losing it
+        const double now = now_s();
+        for (uint32_t i = 0; i < B; i++) {
+            L.st[i] = rc;
+            lane_emit(s, L, i, now);
         }
         L.reqs.clear();
-        return rc;
+        return fail(rc, std::string("server lane launch failed: ") +
+                            hipGetErrorString(hipGetLastError()));
     }
-    HIP_TRY(hipMemcpyAsync(L.h_cw, L.d_cw, (size_t)B * kCwStride * 8, hipMemcpyDeviceToHost,
-                           L.stream));
-    HIP_TRY(hipMemcpyAsync(L.h_q, L.d_q, (size_t)B * 8, hipMemcpyDeviceToHost, L.stream));
-    HIP_TRY(hipMemcpyAsync(L.h_chk, L.d_chk, (size_t)B * 8, hipMemcpyDeviceToHost, L.stream));
-    HIP_TRY(hipMemcpyAsync(L.h_ab, L.d_ab, B, hipMemcpyDeviceToHost, L.stream));
-    HIP_TRY(hipMemcpyAsync(L.h_st, L.d_st, (size_t)B * 4, hipMemcpyDeviceToHost, L.stream));
-    HIP_TRY(hipEventRecord(L.done, L.stream));
     L.busy = true;
-    s->running += B;
     return GRAND_OK;
 }
 
-// Collect a finished lane's results.
-void lane_harvest(grand_server *s, Lane &L, double t)
+// Return the lane's finished requests; all of them once its launch ended.
+int lane_poll(grand_server *s, Lane &L, double t)
 {
-    for (size_t i = 0; i < L.reqs.size(); i++) {
-        const Request &q = L.reqs[i];
-        grand_result r;
-        std::memset(&r, 0, sizeof(r));
-        r.request_id = q.id;
-        std::memcpy(r.codeword, L.h_cw + i * kCwStride, ((q.code->n + 63) / 64) * 8);
-        r.queries = L.h_q[i];
-        r.checks = L.h_chk[i];
-        r.status = L.h_st[i];
-        r.abandoned = L.h_ab[i];
-        r.arrival_s = q.arrival_s;
-        r.submit_s = q.submit_s;
-        r.complete_s = t;
-        s->done.push_back(r);
-        s->mem_in_use -= q.bytes;
-        s->inflight--;
+    for (uint32_t i = 0; i < (uint32_t)L.reqs.size() && L.left; i++)
+        if (!L.taken[i] && __atomic_load_n(&L.flag[i], __ATOMIC_ACQUIRE) == L.seq)
+            lane_emit(s, L, i, t);
+    const hipError_t e = hipEventQuery(L.done);
+    if (e == hipSuccess) {
+        for (uint32_t i = 0; i < (uint32_t)L.reqs.size() && L.left; i++)
+            if (!L.taken[i])
+                lane_emit(s, L, i, t);
+        L.reqs.clear();
+        L.busy = false;
+    } else if (e != hipErrorNotReady) {
+        return fail(GRAND_EDEVICE, std::string("server lane: ") + hipGetErrorString(e));
     }
-    s->running -= L.reqs.size();
-    L.reqs.clear();
-    L.busy = false;
-}
-
-template <typename T>
-int coherent_alloc(T **h, size_t count, T **d)
-{
-    if (hipHostMalloc((void **)h, count * sizeof(T), hipHostMallocCoherent | hipHostMallocMapped) !=
-        hipSuccess) {
-        *h = nullptr;
-        return fail(GRAND_ENOMEM, "hipHostMalloc failed for the serving ring");
-    }
-    std::memset(*h, 0, count * sizeof(T));
-    HIP_TRY(hipHostGetDevicePointer((void **)d, *h, 0));
     return GRAND_OK;
-}
-
-void pers_free(Persist &P)
-{
-    if (P.stream && P.ctl) {
-        __atomic_store_n(&P.ctl->stop, 1u, __ATOMIC_RELEASE);
-        (void)hipStreamSynchronize(P.stream);
-    }
-    (void)hipHostFree(P.ctl);
-    (void)hipHostFree(P.done);
-    (void)hipHostFree(P.jobs);
-    (void)hipHostFree(P.codes);
-    (void)hipHostFree(P.rx);
-    (void)hipHostFree(P.cw);
-    (void)hipHostFree(P.q);
-    (void)hipHostFree(P.chk);
-    (void)hipHostFree(P.ab);
-    (void)hipHostFree(P.st);
-    (void)hipFree(P.dev);
-    (void)hipFree(P.scratch);
-    (void)hipFree(P.queue);
-    if (P.kdone)
-        (void)hipEventDestroy(P.kdone);
-    if (P.stream)
-        (void)hipStreamDestroy(P.stream);
-}
-
-int pers_init(Persist &P, DeviceCtx *ctx, uint32_t ring)
-{
-    P.ring = ring;
-    P.t = tuning_for(0, 0);
-    P.grid = std::max(1u, std::min<uint32_t>(ring, P.t.grid_per_cu * (uint32_t)ctx->cus));
-    int khz = 0;
-    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
-    P.idle_ticks = (uint64_t)(std::max(khz, 1) * 1e3 * kIdleSeconds);
-    HIP_TRY(hipStreamCreateWithFlags(&P.stream, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&P.kdone, hipEventDisableTiming));
-    ServeArgs &a = P.args;
-    KernelArgs &b = a.base;
-    int rc;
-    DevJob *d_jobs;
-    DevCode *d_codes;
-    float *d_rx;
-    if ((rc = coherent_alloc(&P.ctl, 1, &a.ctl)) || (rc = coherent_alloc(&P.done, ring, &a.done)) ||
-        (rc = coherent_alloc(&P.jobs, ring, &d_jobs)) ||
-        (rc = coherent_alloc(&P.codes, ring, &d_codes)) ||
-        (rc = coherent_alloc(&P.rx, (size_t)ring * kSlotFloats, &d_rx)) ||
-        (rc = coherent_alloc(&P.cw, (size_t)ring * kCwStride, &b.cw_out)) ||
-        (rc = coherent_alloc(&P.q, ring, &b.q_out)) ||
-        (rc = coherent_alloc(&P.chk, ring, &b.checks_out)) ||
-        (rc = coherent_alloc(&P.ab, ring, &b.ab_out)) ||
-        (rc = coherent_alloc(&P.st, ring, &b.status_out)))
-        return rc;
-    const uint64_t slot_bytes = node_layout(P.t.node_cap).total;
-    if (hipMalloc((void **)&P.dev, sizeof(ServeDev)) != hipSuccess ||
-        hipMalloc((void **)&P.scratch, (size_t)P.grid * slot_bytes) != hipSuccess ||
-        hipMalloc((void **)&P.queue, 256) != hipSuccess)
-        return fail(GRAND_ENOMEM, "hipMalloc failed for the serving kernel's store");
-    P.busy.assign(ring, 0);
-    b.codes = d_codes;
-    b.jobs = d_jobs;
-    b.njobs = ring;
-    b.low_bits = P.t.low_bits;
-    b.first_band = P.t.first_band;
-    b.band_growth = P.t.band_growth;
-    b.node_cap = P.t.node_cap;
-    b.ni = kMaxItems;
-    b.rx = d_rx;
-    b.queue = P.queue;
-    b.scratch = P.scratch;
-    a.dev = P.dev;
-    a.ring = ring;
-    a.idle_ticks = P.idle_ticks;
-    return GRAND_OK;
-}
-
-bool pers_running(Persist &P)
-{
-    return P.launched && hipEventQuery(P.kdone) == hipErrorNotReady;
-}
-
-// Relaunch the kernel when it is not resident and published requests wait.
-int pers_kick(Persist &P)
-{
-    if (P.live.empty() || pers_running(P))
-        return GRAND_OK;
-    ServeArgs a = P.args;
-    a.start = P.live.begin()->first;
-    if (launch_serve(a, P.grid, P.t.block, P.stream))
-        return fail(GRAND_EDEVICE, std::string("serving kernel launch failed: ") +
-                                       hipGetErrorString(hipGetLastError()));
-    HIP_TRY(hipEventRecord(P.kdone, P.stream));
-    P.launched = true;
-    return GRAND_OK;
-}
-
-// Publish admitted requests into free ring slots, in order.
-int pers_publish(grand_server *s)
-{
-    Persist &P = *s->pers;
-    uint64_t t = P.tail;
-    while (!s->pending.empty()) {
-        const uint32_t slot = (uint32_t)(t % P.ring);
-        if (P.busy[slot])
-            break;   // slot still holds request t - ring: publish in order later
-        Request &q = s->pending.front();
-        const grand_code *c = q.code;
-        P.codes[slot] = DevCode{c->n, c->rows, c->kw, c->row_w32, c->d_rows, c->d_cols};
-        P.jobs[slot] = DevJob{slot, q.M, (uint64_t)slot * kSlotFloats, q.cap, slot, 0};
-        std::memcpy(P.rx + (size_t)slot * kSlotFloats, q.rx.data(), q.rx.size() * sizeof(float));
-        P.busy[slot] = 1;
-        P.live.emplace(t, std::move(q));
-        s->pending.pop_front();
-        t++;
-    }
-    if (t != P.tail) {
-        // the slot writes above become visible before the new count
-        __atomic_store_n(&P.ctl->tail, t, __ATOMIC_RELEASE);
-        P.tail = t;
-    }
-    s->running = P.live.size();
-    return pers_kick(P);
-}
-
-// Harvest finished slots.
-void pers_harvest(grand_server *s, double t)
-{
-    Persist &P = *s->pers;
-    for (auto it = P.live.begin(); it != P.live.end();) {
-        const uint64_t idx = it->first;
-        const uint32_t slot = (uint32_t)(idx % P.ring);
-        if (__atomic_load_n(&P.done[slot], __ATOMIC_ACQUIRE) != idx + 1) {
-            ++it;
-            continue;
-        }
-        const Request &q = it->second;
-        grand_result r;
-        std::memset(&r, 0, sizeof(r));
-        r.request_id = q.id;
-        std::memcpy(r.codeword, P.cw + (size_t)slot * kCwStride, ((q.code->n + 63) / 64) * 8);
-        r.queries = P.q[slot];
-        r.checks = P.chk[slot];
-        r.status = P.st[slot];
-        r.abandoned = P.ab[slot];
-        r.arrival_s = q.arrival_s;
-        r.submit_s = q.submit_s;
-        r.complete_s = t;
-        s->done.push_back(r);
-        s->mem_in_use -= q.bytes;
-        s->inflight--;
-        P.busy[slot] = 0;
-        it = P.live.erase(it);
-    }
-    s->running = P.live.size();
 }
 
 int validate_request(const grand_code *code, const float *rx, uint32_t M, float noise_var,
@@ -497,7 +327,7 @@ int submit_locked(grand_server *s, const grand_code *code, const float *rx, uint
     s->mem_in_use += bytes;
     if (id)
         *id = s->pending.back().id;
-    return s->pers ? pers_publish(s) : GRAND_OK;
+    return GRAND_OK;
 }
 
 int drain_done(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *n_out)
@@ -515,26 +345,12 @@ int drain_done(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *n
 int poll_locked(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *n_out)
 {
     const double t = now_s();
-    if (s->pers) {
-        pers_harvest(s, t);
-        if (s->pers->launched) {
-            hipError_t e = hipEventQuery(s->pers->kdone);
-            if (e != hipSuccess && e != hipErrorNotReady)
-                return fail(GRAND_EDEVICE, std::string("serving kernel: ") + hipGetErrorString(e));
-        }
-        int rc = pers_publish(s);
-        if (rc)
-            return rc;
-        return drain_done(s, out, max_out, n_out);
-    }
     for (auto &L : s->lanes) {
         if (!L->busy)
             continue;
-        hipError_t e = hipEventQuery(L->done);
-        if (e == hipSuccess)
-            lane_harvest(s, *L, t);
-        else if (e != hipErrorNotReady)
-            return fail(GRAND_EDEVICE, std::string("server lane: ") + hipGetErrorString(e));
+        int rc = lane_poll(s, *L, t);
+        if (rc)
+            return rc;
     }
     for (auto &L : s->lanes) {
         if (s->pending.empty())
@@ -565,15 +381,12 @@ int grand_server_create(const grand_server_config *cfg, grand_server **out)
 {
     if (!cfg || !out)
         return fail(GRAND_EINVAL, "null pointer");
-    if (cfg->max_inflight < 1 || cfg->max_inflight > (1u << 20) || cfg->memory_budget == 0 ||
-        (cfg->mode != GRAND_SERVE_LANES && cfg->mode != GRAND_SERVE_PERSISTENT) ||
-        (cfg->mode == GRAND_SERVE_LANES && (cfg->lanes < 1 || cfg->lanes > 8 ||
-                                            cfg->max_batch < 1 || cfg->max_batch > 65536)))
-        return fail(GRAND_EINVAL, "invalid server configuration");
-    // Switched off: a GPU run of this mode did not finish and the cause is
-    // not established.  The code below stays unreachable until it is.
     if (cfg->mode == GRAND_SERVE_PERSISTENT)
-        return fail(GRAND_EINVAL, "persistent serving mode is disabled");
+        return fail(GRAND_EINVAL, "persistent serving mode is not available");
+    if (cfg->max_inflight < 1 || cfg->max_inflight > (1u << 20) || cfg->memory_budget == 0 ||
+        cfg->mode != GRAND_SERVE_LANES || cfg->lanes < 1 || cfg->lanes > 32 ||
+        cfg->max_batch < 1 || cfg->max_batch > 65536)
+        return fail(GRAND_EINVAL, "invalid server configuration");
     DeviceCtx *ctx;
     int rc = current_ctx(&ctx);
     if (rc)
@@ -581,20 +394,14 @@ int grand_server_create(const grand_server_config *cfg, grand_server **out)
     auto s = std::make_unique<grand_server>();
     s->cfg = *cfg;
     s->ctx = ctx;
-    if (cfg->mode == GRAND_SERVE_PERSISTENT) {
-        s->pers = std::make_unique<Persist>();
-        rc = pers_init(*s->pers, ctx, cfg->max_inflight);
-        if (rc) {
-            pers_free(*s->pers);
-            return rc;
-        }
-        *out = s.release();
-        return GRAND_OK;
-    }
     const uint32_t per_lane = std::min(cfg->max_batch, cfg->max_inflight);
+    // workgroups per launch: together the lanes may hold twice the resident
+    // capacity of the device
+    const grand_tuning t = tuning_for(0, 0);
+    const uint32_t grid = std::max(64u, 2 * t.grid_per_cu * (uint32_t)ctx->cus / cfg->lanes);
     for (uint32_t i = 0; i < cfg->lanes; i++) {
         auto L = std::make_unique<Lane>();
-        rc = lane_init(*L, per_lane);
+        rc = lane_init(*L, per_lane, grid);
         if (rc) {
             lane_free(*L);
             for (auto &x : s->lanes)
@@ -613,8 +420,6 @@ void grand_server_destroy(grand_server *s)
         return;
     for (auto &L : s->lanes)
         lane_free(*L);
-    if (s->pers)
-        pers_free(*s->pers);
     delete s;
 }
 

@@ -98,7 +98,7 @@ def test_server_configuration_rejected_on_host():
     from paper_2405_01808_amd import _native as nat
     L = nat.lib()
     out = ctypes.c_void_p()
-    for cfg in [(0, 1, 1, 0, 1 << 20), (4, 0, 1, 0, 1 << 20), (4, 9, 1, 0, 1 << 20),
+    for cfg in [(0, 1, 1, 0, 1 << 20), (4, 0, 1, 0, 1 << 20), (4, 33, 1, 0, 1 << 20),
                 (4, 1, 0, 0, 1 << 20), (4, 1, 1, 0, 0), ((1 << 20) + 1, 1, 1, 0, 1 << 20),
                 (4, 1, 1, 2, 1 << 20), (0, 0, 0, 1, 1 << 20), (4, 0, 0, 1, 0),
                 (4, 1, 1, 1, 1 << 20)]:   # persistent mode is switched off
