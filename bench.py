@@ -28,6 +28,9 @@ WORKLOAD_DESC = ("Polar N=128 K=64 (PW frozen set), Gray 16-QAM, AWGN Eb/N0 unif
                  "8192 codewords per step in one persistent launch, query cap 2^16")
 ALU_PEAK = 256 * 64 * 2.4e9          # 32-bit integer lane-ops/s (256 CU x 64 lanes x 2.4 GHz)
 STEP_WEIGHTS = os.path.join(ROOT, "tests", "golden", "step_weights_polar128_16qam.json")
+SERVE_LANES = 12                     # server streams, each on its own hardware queue
+SERVE_BATCH = 256                    # requests per server launch at most
+HW_QUEUES = "16"                     # HIP hardware queues for this process (HIP's default is 4)
 COPY_BYTES = 256 << 20               # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grand_decode_kernel_polar128_16qam_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_01808_amd", "csrc", "grand_kernels.hip")
@@ -84,9 +87,13 @@ def serving(g, w, count: int, plain_count: int):
     trace = g.Trace(order, idx, [j.M for j in jobs], [j.cap for j in jobs],
                     [j.noise_var for j in jobs], [j.rx for j in jobs], arrivals)
 
-    def replay(persistent):
-        srv = g.Server(max_inflight=16384, lanes=8, max_batch=2048, memory_budget=48 << 30,
-                       persistent=persistent)
+    warm = g.Trace(order, idx[:2000], [j.M for j in jobs[:2000]], [j.cap for j in jobs[:2000]],
+                   [j.noise_var for j in jobs[:2000]], [j.rx for j in jobs[:2000]], arrivals[:2000])
+
+    def replay():
+        srv = g.Server(max_inflight=16384, lanes=SERVE_LANES, max_batch=SERVE_BATCH,
+                       memory_budget=48 << 30)
+        warm.run_server(srv)          # first launches, code objects, page mappings
         res, wall = trace.run_server(srv)
         srv.close()
         assert all(r.status == 0 for r in res), "server request errors"
@@ -94,19 +101,21 @@ def serving(g, w, count: int, plain_count: int):
         groups = {}
         for j, l in zip(jobs, lat):
             groups.setdefault((j.N, j.M), []).append(l)
-        mode = "persistent" if persistent else "lanes"
+        mode = "lanes"
         for k in sorted(groups, key=lambda k: -np.percentile(groups[k], 99))[:6]:
             log(f"serving[{mode}] (N, M)={k}: n={len(groups[k])} "
                 f"p50 {np.percentile(groups[k], 50):.3f} ms p99 {np.percentile(groups[k], 99):.3f} ms")
         q = np.array([r.queries for r in res], dtype=np.float64)
-        return res, {"mode": mode, "requests": len(jobs), "arrival_rate": 2e5, "wall_s": wall,
+        return res, {"mode": mode, "lanes": SERVE_LANES, "max_batch": SERVE_BATCH,
+                     "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")),
+                     "requests": len(jobs), "arrival_rate": 2e5, "wall_s": wall,
                      "p50_ms": float(np.percentile(lat, 50)),
                      "p99_ms": float(np.percentile(lat, 99)),
                      "max_ms": float(lat.max()),
                      "codewords_per_s": len(jobs) / wall, "checks_per_s": float(q.sum()) / wall,
                      "abandon_rate": float(np.mean([r.abandoned for r in res]))}
 
-    res, out = replay(False)
+    res, out = replay()
     if plain_count:
         sub = jobs[:plain_count]
         ptrace = g.Trace(order, idx[:plain_count], [j.M for j in sub], [j.cap for j in sub],
@@ -146,6 +155,9 @@ def main():
                                    "(codewords are independent: see the sharding note)"}))
         sys.exit(2)
 
+    # more hardware queues than server lanes plus the other streams, so every
+    # lane's launches run side by side (read by HIP when it initialises)
+    os.environ["GPU_MAX_HW_QUEUES"] = HW_QUEUES
     import torch
     import workload as w
     import paper_2405_01808_amd as g
