@@ -136,6 +136,41 @@ def serving(g, w, count: int, plain_count: int):
     return out
 
 
+def latency(g, w, reps: int):
+    """One N=1024 256-QAM codeword (cap 2^20) per call, `reps` different
+    codewords: host-to-host grand_decode, and the device launch alone."""
+    import torch
+    jobs = w.config_jobs("polar1024_256qam", count=reps)
+    code = g.Code(1024, w.polar_code(1024, 512).h_rows)
+    host_ms, dev_ms, qs, abs_ = [], [], [], []
+    for j in jobs:
+        t0 = time.perf_counter()
+        _, q, ab = g.decode(code, j.rx, j.M, j.noise_var, j.cap)
+        host_ms.append((time.perf_counter() - t0) * 1e3)
+        qs.append(q)
+        abs_.append(ab)
+    stream = torch.cuda.current_stream()
+    for j in jobs:
+        rx = torch.from_numpy(j.rx).cuda()
+        plan = g.BatchPlan([code], np.zeros(1, np.uint32), [j.M], [j.cap], [j.noise_var],
+                           np.zeros(1, np.uint64), rx)
+        plan.launch(stream)          # first use of this plan's buffers
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.launch(stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        dev_ms.append(a.elapsed_time(b))
+    return {"workload": "polar1024_256qam: N=1024 K=512, 256-QAM, Eb/N0 in {10,12,14} dB, "
+                        "cap 2^20, one codeword per call", "reps": reps,
+            "host_p50_ms": float(np.percentile(host_ms, 50)),
+            "host_p99_ms": float(np.percentile(host_ms, 99)),
+            "device_p50_ms": float(np.percentile(dev_ms, 50)),
+            "device_p99_ms": float(np.percentile(dev_ms, 99)),
+            "mean_q": float(np.mean(qs)), "abandon_rate": float(np.mean(abs_))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +181,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--plain-count", type=int, default=2000)
+    ap.add_argument("--latency-reps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB three times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -253,6 +289,10 @@ def main():
         t0 = time.time()
         result["serving"] = serving(g, w, args.serve_count, args.plain_count)
         log(f"serving replay done in {time.time() - t0:.1f}s")
+    if args.latency_reps:
+        t0 = time.time()
+        result["latency"] = latency(g, w, args.latency_reps)
+        log(f"latency mode done in {time.time() - t0:.1f}s")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(jobs, min(args.cpu_sample, len(jobs)))
         n = len(cb["q"])

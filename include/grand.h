@@ -137,6 +137,29 @@ typedef struct {
 int grand_decode_batch(const grand_batch *batch, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Batch graphs (for callers that decode batches of one fixed shape    */
+/* over and over, e.g. a receiver's frames: one call per batch)        */
+/* ------------------------------------------------------------------ */
+
+/* grand_graph_create validates and plans `batch` exactly as
+ * grand_decode_batch does, copies its job table to the device, and records
+ * the launches as a HIP graph.  Each launch in the graph is preceded by a
+ * kernel that zeroes its work counter, so every replay starts from the same
+ * state.  The host arrays of `batch` are read only during the call.  The
+ * graph keeps the batch's device pointers (rx and the outputs) and the codes'
+ * device matrices: the caller keeps them alive until grand_graph_destroy and
+ * may rewrite rx between launches.  grand_graph_launch enqueues one replay on
+ * `stream` (a hipStream_t; NULL = the default stream).  Each replay writes
+ * what grand_decode_batch would write for the rx it finds.  Replays of one
+ * graph must not overlap: issue them on one stream, or order them.
+ * Errors: GRAND_EINVAL (null pointer, empty or invalid batch), GRAND_ENOMEM,
+ * GRAND_EDEVICE. */
+typedef struct grand_graph grand_graph;
+int grand_graph_create(const grand_batch *batch, grand_graph **out);
+int grand_graph_launch(grand_graph *graph, void *stream);
+void grand_graph_destroy(grand_graph *graph);
+
+/* ------------------------------------------------------------------ */
 /* Launch-shape tuning                                                 */
 /* ------------------------------------------------------------------ */
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "grand_decode", "grand_decode_batch", "grand_tuning_get", "grand_tuning_set",
     "grand_request_bytes", "grand_server_create", "grand_server_destroy", "grand_server_submit",
     "grand_server_cancel", "grand_server_poll", "grand_server_stats", "grand_server_run_trace",
-    "grand_plain_run_trace",
+    "grand_plain_run_trace", "grand_graph_create", "grand_graph_launch", "grand_graph_destroy",
 ]
 
 
@@ -106,6 +106,12 @@ def lib():
     L.grand_decode.restype = i32
     L.grand_decode_batch.argtypes = [ctypes.POINTER(GrandBatch), vp]
     L.grand_decode_batch.restype = i32
+    L.grand_graph_create.argtypes = [ctypes.POINTER(GrandBatch), ctypes.POINTER(vp)]
+    L.grand_graph_create.restype = i32
+    L.grand_graph_launch.argtypes = [vp, vp]
+    L.grand_graph_launch.restype = i32
+    L.grand_graph_destroy.argtypes = [vp]
+    L.grand_graph_destroy.restype = None
     L.grand_tuning_get.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]
     L.grand_tuning_get.restype = i32
     L.grand_tuning_set.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]

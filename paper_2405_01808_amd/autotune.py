@@ -1,0 +1,82 @@
+"""Launch-shape autotuner for one (n, M) bucket.
+
+Times candidate tunings (grand_tuning_set) on a sample batch of that bucket,
+keeps only candidates whose outputs equal the first candidate's (a tuning
+changes the launch shape, never a result; a candidate whose node store
+overflows reports GRAND_ECAPACITY and is dropped), and installs the fastest.
+Batches decoded afterwards use it for every launch of that bucket (merged
+launches of mixed batches use the (0, 0) entry)."""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+from . import decoder
+
+
+def default_candidates(n: int, M: int) -> list[dict]:
+    base = decoder.get_tuning(n, M)
+    out = []
+    for low_bits, grid in itertools.product((8, 9, 10), (6, 7, 8)):
+        c = dict(base)
+        c.update(low_bits=low_bits, grid_per_cu=grid)
+        out.append(c)
+    return out
+
+
+def autotune(code, M: int, rx, rx_offset, cap, noise_var, candidates=None, reps: int = 3,
+             stream=None) -> dict:
+    """rx: float32 device tensor holding the sample words at rx_offset (one
+    per word, all of `code` and modulation M).  Returns the chosen tuning,
+    its median launch time and every candidate's timing."""
+    import torch
+    n = code.n
+    count = len(rx_offset)
+    cands = candidates if candidates is not None else default_candidates(n, M)
+    if not cands:
+        raise ValueError("no candidate tunings")
+    original = decoder.get_tuning(n, M)
+    stream = stream or torch.cuda.current_stream(rx.device)
+    ref = None
+    table = []
+    try:
+        for c in cands:
+            try:
+                decoder.set_tuning(n, M, **c)
+            except Exception as e:   # an invalid tuning for this device
+                table.append({"tuning": c, "ms": None, "rejected": str(e)})
+                continue
+            plan = decoder.BatchPlan([code], np.zeros(count, np.uint32), [M] * count,
+                                     np.asarray(cap, np.uint64), np.asarray(noise_var, np.float32),
+                                     rx_offset, rx)
+            plan.launch(stream)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                out = plan.launch(stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b))
+            res = [t.cpu().numpy().copy() for t in (out.codewords, out.queries, out.abandoned,
+                                                     out.status)]
+            if np.any(res[3][:count] != 0):
+                table.append({"tuning": c, "ms": None, "rejected": "device status errors"})
+                continue
+            if ref is None:
+                ref = res
+            elif not all(np.array_equal(x[:count], y[:count]) for x, y in zip(res, ref)):
+                table.append({"tuning": c, "ms": None, "rejected": "results differ"})
+                continue
+            table.append({"tuning": c, "ms": float(np.median(times))})
+    finally:
+        decoder.set_tuning(n, M, **original)
+    ok = [t for t in table if t["ms"] is not None]
+    if not ok:
+        raise RuntimeError("no candidate tuning decoded the sample")
+    best = min(ok, key=lambda t: t["ms"])
+    decoder.set_tuning(n, M, **best["tuning"])
+    return {"n": n, "M": M, "best": best["tuning"], "ms": best["ms"], "table": table}

@@ -209,13 +209,20 @@ struct Bucket {
     uint32_t ni = 0;   // LDS sizing: next_pow2(2L) of the bucket's largest word
 };
 
-// Enqueue one launch per bucket; jobs/codes already staged in device memory.
-int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buckets,
-                    const std::vector<uint32_t> &job_base, const float *rx, uint64_t *cw_out,
-                    uint64_t *q_out, uint8_t *ab_out, int32_t *status_out, uint64_t *checks_out,
-                    void *stream)
+// Where a group of launches runs: staged tables, work counters and stores.
+struct LaunchTarget {
+    const DevCode *codes;
+    const DevJob *jobs;
+    unsigned long long *queues;   // one counter per bucket (index mod 64)
+    uint64_t *qnext;              // counter values at launch, or null: zero each
+                                  // counter in the stream before its launch
+    uint8_t *scratch;
+};
+
+// Workgroups per launch of each bucket and the store bytes they need.
+size_t bucket_grids(DeviceCtx *ctx, const std::vector<Bucket> &buckets, std::vector<uint32_t> &grids)
 {
-    std::vector<uint32_t> grids(buckets.size());
+    grids.assign(buckets.size(), 1);
     size_t need = 0;
     for (size_t i = 0; i < buckets.size(); i++) {
         const grand_tuning &t = buckets[i].t;
@@ -224,14 +231,20 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
         grids[i] = std::max(1u, g);
         need = std::max<size_t>(need, (size_t)grids[i] * node_layout(t.node_cap).total);
     }
-    int rc = ensure_scratch(r, need);
-    if (rc)
-        return rc;
+    return need;
+}
+
+// Enqueue one launch per bucket; jobs/codes already staged in device memory.
+int enqueue_buckets(const LaunchTarget &lt, const std::vector<Bucket> &buckets,
+                    const std::vector<uint32_t> &grids, const std::vector<uint32_t> &job_base,
+                    const float *rx, uint64_t *cw_out, uint64_t *q_out, uint8_t *ab_out,
+                    int32_t *status_out, uint64_t *checks_out, void *stream)
+{
     for (size_t i = 0; i < buckets.size(); i++) {
         const grand_tuning &t = buckets[i].t;
         KernelArgs a;
-        a.codes = r.codes;
-        a.jobs = r.jobs + job_base[i];
+        a.codes = lt.codes;
+        a.jobs = lt.jobs + job_base[i];
         a.njobs = (uint32_t)buckets[i].words.size();
         a.low_bits = t.low_bits;
         a.first_band = t.first_band;
@@ -244,28 +257,29 @@ int enqueue_buckets(DeviceCtx *ctx, StreamRes &r, const std::vector<Bucket> &buc
         a.ab_out = ab_out;
         a.status_out = status_out;
         a.checks_out = checks_out;
-        a.queue = r.queues + (i % 64);
-        a.qbase = r.qnext[i % 64];
-        a.scratch = r.scratch;
+        a.queue = lt.queues + (i % 64);
+        a.qbase = lt.qnext ? lt.qnext[i % 64] : 0;
+        a.scratch = lt.scratch;
         a.done_out = nullptr;
         a.done_seq = 0;
         a.pad2 = 0;
+        if (!lt.qnext && launch_zero(a.queue, 1, stream))
+            return fail(GRAND_EDEVICE, "counter reset launch failed");
         if (launch_decode(a, grids[i], t.block, stream))
             return fail(GRAND_EDEVICE, std::string("decode kernel launch failed: ") +
                                            hipGetErrorString(hipGetLastError()));
-        r.qnext[i % 64] += a.njobs + grids[i];
+        if (lt.qnext)
+            lt.qnext[i % 64] += a.njobs + grids[i];
     }
     return GRAND_OK;
 }
 
-// Validate a batch, bucket it by (n, M), stage its jobs and enqueue the
-// launches on `stream` using the buffers of `r`.
-int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream, int mixed)
+// Validate a batch and group its words into launches ("buckets"), each in
+// the order its workgroups should take them.
+int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Bucket> &buckets)
 {
     if (!b)
         return fail(GRAND_EINVAL, "null batch");
-    if (b->count == 0)
-        return GRAND_OK;
     if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
         !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
         return fail(GRAND_EINVAL, "null pointer in batch");
@@ -275,7 +289,7 @@ int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *st
         if (!b->codes[c] || b->codes[c]->device != ctx->device)
             return fail(GRAND_EINVAL, "null code or code on another device");
     std::map<std::pair<uint32_t, uint32_t>, size_t> index;
-    std::vector<Bucket> buckets;
+    buckets.clear();
     for (uint32_t i = 0; i < b->count; i++) {
         uint32_t ci = b->code_index[i];
         if (ci >= b->n_codes)
@@ -331,7 +345,37 @@ int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *st
             std::stable_sort(bk.words.begin(), bk.words.end(), [&](uint32_t x, uint32_t y) {
                 return b->query_cap[x] > b->query_cap[y];
             });
-    int rc = init_stream_res(r);
+    return GRAND_OK;
+}
+
+// Job and code tables of a planned batch, jobs in bucket order.
+void fill_tables(const grand_batch *b, const std::vector<Bucket> &buckets, DevJob *jobs,
+                 DevCode *codes, std::vector<uint32_t> &job_base)
+{
+    for (uint32_t c = 0; c < b->n_codes; c++) {
+        const grand_code *cd = b->codes[c];
+        codes[c] = DevCode{cd->n, cd->rows, cd->kw, cd->row_w32, cd->d_rows, cd->d_cols};
+    }
+    job_base.clear();
+    uint32_t k = 0;
+    for (auto &bk : buckets) {
+        job_base.push_back(k);
+        for (uint32_t i : bk.words)
+            jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i], i, 0};
+    }
+}
+
+// Validate a batch, bucket it by (n, M), stage its jobs and enqueue the
+// launches on `stream` using the buffers of `r`.
+int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream, int mixed)
+{
+    if (b && b->count == 0)
+        return GRAND_OK;
+    std::vector<Bucket> buckets;
+    int rc = plan_batch(ctx, b, mixed, buckets);
+    if (rc)
+        return rc;
+    rc = init_stream_res(r);
     if (rc)
         return rc;
     if (r.staged_pending) {
@@ -347,18 +391,8 @@ int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *st
         rc = ensure_pinned(&r.h_jobs, &r.h_jobs_cap, b->count);
     if (rc)
         return rc;
-    for (uint32_t c = 0; c < b->n_codes; c++) {
-        const grand_code *cd = b->codes[c];
-        r.h_codes[c] = DevCode{cd->n, cd->rows, cd->kw, cd->row_w32, cd->d_rows, cd->d_cols};
-    }
     std::vector<uint32_t> job_base;
-    uint32_t k = 0;
-    for (auto &bk : buckets) {
-        job_base.push_back(k);
-        for (uint32_t i : bk.words)
-            r.h_jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i],
-                                   i, 0};
-    }
+    fill_tables(b, buckets, r.h_jobs, r.h_codes, job_base);
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(r.codes, r.h_codes, b->n_codes * sizeof(DevCode),
                            hipMemcpyHostToDevice, st));
@@ -366,7 +400,12 @@ int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *st
                            st));
     HIP_TRY(hipEventRecord(r.staged, st));
     r.staged_pending = true;
-    return enqueue_buckets(ctx, r, buckets, job_base, b->rx, b->codeword_out, b->queries_out,
+    std::vector<uint32_t> grids;
+    rc = ensure_scratch(r, bucket_grids(ctx, buckets, grids));
+    if (rc)
+        return rc;
+    const LaunchTarget lt{r.codes, r.jobs, r.queues, r.qnext, r.scratch};
+    return enqueue_buckets(lt, buckets, grids, job_base, b->rx, b->codeword_out, b->queries_out,
                            b->abandoned_out, b->status_out, b->checks_out, stream);
 }
 
@@ -536,8 +575,12 @@ int grand_decode(const grand_code *code, const float *rx, uint32_t M, float nois
     Bucket bk{code->n, M, tuning_for(code->n, M), {0}};
     bk.t.grid_per_cu = 1;
     std::vector<Bucket> buckets{bk};
-    std::vector<uint32_t> base{0};
-    rc = enqueue_buckets(ctx, *r, buckets, base, r->d_rx, r->d_out, r->d_out + kCwStride,
+    std::vector<uint32_t> base{0}, grids;
+    rc = ensure_scratch(*r, bucket_grids(ctx, buckets, grids));
+    if (rc)
+        return rc;
+    const LaunchTarget lt{r->codes, r->jobs, r->queues, r->qnext, r->scratch};
+    rc = enqueue_buckets(lt, buckets, grids, base, r->d_rx, r->d_out, r->d_out + kCwStride,
                          r->d_ab, r->d_status, r->d_out + kCwStride + 1, st);
     if (rc)
         return rc;
@@ -553,6 +596,103 @@ int grand_decode(const grand_code *code, const float *rx, uint32_t M, float nois
     std::memcpy(codeword_out, r->h_out, w64 * sizeof(uint64_t));
     *queries_out = r->h_out[kCwStride];
     *abandoned_out = r->h_ab[0];
+    return GRAND_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+
+struct grand_graph {
+    int device = -1;
+    DevJob *jobs = nullptr;
+    DevCode *codes = nullptr;
+    unsigned long long *queues = nullptr;
+    uint8_t *scratch = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void grand_graph_destroy(grand_graph *g)
+{
+    if (!g)
+        return;
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    (void)hipFree(g->jobs);
+    (void)hipFree(g->codes);
+    (void)hipFree(g->queues);
+    (void)hipFree(g->scratch);
+    delete g;
+}
+
+int grand_graph_create(const grand_batch *b, grand_graph **out)
+{
+    if (!b || !out)
+        return fail(GRAND_EINVAL, "null pointer");
+    if (b->count == 0)
+        return fail(GRAND_EINVAL, "empty batch");
+    DeviceCtx *ctx;
+    int rc = current_ctx(&ctx);
+    if (rc)
+        return rc;
+    std::vector<Bucket> buckets;
+    rc = plan_batch(ctx, b, -1, buckets);
+    if (rc)
+        return rc;
+    std::vector<DevJob> jobs(b->count);
+    std::vector<DevCode> codes(b->n_codes);
+    std::vector<uint32_t> job_base, grids;
+    fill_tables(b, buckets, jobs.data(), codes.data(), job_base);
+    const size_t need = bucket_grids(ctx, buckets, grids);
+    auto g = new grand_graph;
+    g->device = ctx->device;
+    hipStream_t cs = nullptr;
+    auto bail = [&](int code) {
+        if (cs)
+            (void)hipStreamDestroy(cs);
+        grand_graph_destroy(g);
+        return code;
+    };
+    const uint32_t nq = (uint32_t)std::min<size_t>(buckets.size(), 64);
+    if (hipMalloc((void **)&g->jobs, jobs.size() * sizeof(DevJob)) != hipSuccess ||
+        hipMalloc((void **)&g->codes, codes.size() * sizeof(DevCode)) != hipSuccess ||
+        hipMalloc((void **)&g->queues, nq * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&g->scratch, std::max<size_t>(need, 256)) != hipSuccess)
+        return bail(fail(GRAND_ENOMEM, "hipMalloc failed for a batch graph"));
+    if (hipMemcpy(g->jobs, jobs.data(), jobs.size() * sizeof(DevJob), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(g->codes, codes.data(), codes.size() * sizeof(DevCode),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(GRAND_EDEVICE, "staging a batch graph failed"));
+    // every launch zeroes its counter first (a fill kernel, not a memset
+    // node), so each replay starts from the same state
+    const LaunchTarget lt{g->codes, g->jobs, g->queues, nullptr, g->scratch};
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return bail(fail(GRAND_EDEVICE, "hipStreamBeginCapture failed"));
+    rc = enqueue_buckets(lt, buckets, grids, job_base, b->rx, b->codeword_out, b->queries_out,
+                         b->abandoned_out, b->status_out, b->checks_out, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    g->graph = graph;
+    if (rc)
+        return bail(rc);
+    if (e != hipSuccess || !graph)
+        return bail(fail(GRAND_EDEVICE, std::string("hipStreamEndCapture: ") +
+                                            hipGetErrorString(e)));
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(GRAND_EDEVICE, "hipGraphInstantiate failed"));
+    (void)hipStreamDestroy(cs);
+    *out = g;
+    return GRAND_OK;
+}
+
+int grand_graph_launch(grand_graph *g, void *stream)
+{
+    if (!g)
+        return fail(GRAND_EINVAL, "null graph");
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
     return GRAND_OK;
 }
 

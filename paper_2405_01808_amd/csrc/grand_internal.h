@@ -135,5 +135,7 @@ inline uint32_t items_pow2(uint32_t n, uint32_t M)
 // workgroup takes indices until one is past the batch, so the counter
 // advances by exactly njobs + grid.
 int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stream);
+// Zero n 64-bit counters with a kernel (graph-safe, unlike a memset node).
+int launch_zero(unsigned long long *p, uint32_t n, void *stream);
 
 }  // namespace grand

@@ -979,7 +979,19 @@ __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
     }
 }
 
+__global__ void zero_kernel(unsigned long long *p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0;
+}
+
 }  // namespace
+
+int launch_zero(unsigned long long *p, uint32_t n, void *stream)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, p, n);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 
 int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stream)
 {

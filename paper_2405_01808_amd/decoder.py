@@ -124,6 +124,36 @@ class BatchPlan:
         return self.out
 
 
+class BatchGraph:
+    """A BatchPlan recorded once as a HIP graph (grand_graph_*): each launch
+    decodes whatever rx the plan's buffer holds, into the plan's outputs."""
+
+    def __init__(self, plan: BatchPlan):
+        self.plan = plan
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().grand_graph_create(ctypes.byref(plan.desc), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.plan.rx.device)
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        nat.check(nat.lib().grand_graph_launch(self.handle, ctypes.c_void_p(sp)))
+        return self.plan.out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nat.lib().grand_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def decode_batch(codes, code_index, M, cap, noise_var, rx_offset, rx, stream=None) -> BatchResult:
     """Decode many codewords on the GPU (asynchronous on `stream`)."""
     plan = BatchPlan(codes, code_index, M, cap, noise_var, rx_offset, rx)

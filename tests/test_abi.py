@@ -118,3 +118,15 @@ def test_request_bytes_reflects_tuned_store():
     b = g.request_bytes(1024, 4)
     t = g.get_tuning(1024, 4)
     assert b > 18 * t["node_cap"]
+
+
+def test_graph_calls_rejected_on_host():
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    out = ctypes.c_void_p()
+    assert L.grand_graph_create(None, ctypes.byref(out)) == nat.GRAND_EINVAL
+    b = nat.GrandBatch()
+    b.count = 0
+    assert L.grand_graph_create(ctypes.byref(b), ctypes.byref(out)) == nat.GRAND_EINVAL
+    assert L.grand_graph_launch(None, None) == nat.GRAND_EINVAL
+    L.grand_graph_destroy(None)   # no-op
