@@ -113,6 +113,7 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     o = (o + 1) & ~1u;          // 8-byte alignment of the table
     L.lkey = o;  o += 1u << low_bits;
     L.ltmp = o;  o += 1u << low_bits;
+    o = (o + 3) & ~3u;          // 16-byte alignment of the leading words
     L.ls0 = o;   o += (1u << low_bits) + 8;   // padded for 8-wide reads
     L.words = o;
     return L;

@@ -763,13 +763,17 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                     const uint32_t cntk = e - j;
                     const uint32_t ld = S.flead[k];
                     // min over (entry XOR lead) is zero iff a leading word
-                    // matches; reading up to 7 entries past the piece (the
-                    // table is padded) can only cause a spurious rescan below
+                    // matches.  Reads start at the 16-byte boundary below
+                    // the piece and may run up to 7 entries past it (the
+                    // table is aligned and padded): an entry outside the
+                    // piece can only cause a spurious rescan below.
                     uint32_t mn = 0xFFFFFFFFu;
-                    for (uint32_t t = 0; t < cntk; t += 8) {
-                        const uint32_t *q8 = ls0 + l0 + t;
-                        mn = min(mn, min(min(q8[0] ^ ld, q8[1] ^ ld), min(q8[2] ^ ld, q8[3] ^ ld)));
-                        mn = min(mn, min(min(q8[4] ^ ld, q8[5] ^ ld), min(q8[6] ^ ld, q8[7] ^ ld)));
+                    const uint32_t e0 = l0 + cntk;
+                    const uint4 *p4 = reinterpret_cast<const uint4 *>(ls0 + (l0 & ~3u));
+                    for (uint32_t t = l0 & ~3u; t < e0; t += 8, p4 += 2) {
+                        const uint4 x = p4[0], y = p4[1];
+                        mn = min(mn, min(min(x.x ^ ld, x.y ^ ld), min(x.z ^ ld, x.w ^ ld)));
+                        mn = min(mn, min(min(y.x ^ ld, y.y ^ ld), min(y.z ^ ld, y.w ^ ld)));
                     }
                     const bool any = mn == 0;
                     if (any) {   // a leading word matched: verify and keep the best
@@ -958,7 +962,7 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
 __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
 {
     __shared__ Shared sh;
-    extern __shared__ uint32_t dyn[];
+    extern __shared__ __align__(16) uint32_t dyn[];
     const Workspace w = workspace(a, dyn);
     for (;;) {
         if (threadIdx.x == 0) {
