@@ -415,13 +415,17 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nod
                     break;
                 }
                 S.foff[tid] = off;
+                // the slot of child j < blockDim (a thread's first child)
+                for (uint32_t j = off; j < min(off + cnt, bs); j++)
+                    S.fown[j] = tid;
                 if (h < pend && (cnt || !first))
                     nd.cnext[h] = (uint16_t)(lo + cnt);
                 __syncthreads();
                 const uint32_t ncnt = min(bs, pend - c0);
-                uint32_t k = 0;
+                uint32_t k = tid < total ? S.fown[tid] : 0;
                 for (uint32_t j = tid; j < total; j += bs) {
-                    k = flat_owner(S.foff, k, ncnt, j);
+                    if (j >= bs)
+                        k = flat_owner(S.foff, k, ncnt, j);
                     uint32_t r = S.fb[k] + (j - S.foff[k]);
                     uint32_t dst = used + j;
                     nd.cost[dst] = S.fcost[k] + (A.ikey[r] >> 10);
