@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import workload as w
+from helpers import make_plan, outputs
 
 pytestmark = pytest.mark.gpu
 
@@ -16,28 +17,6 @@ def gpu():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     g.init(0)
     return g
-
-
-def make_plan(g, jobs):
-    import torch
-    codes, order, idx = {}, [], []
-    for j in jobs:
-        if (j.N, j.K) not in codes:
-            codes[(j.N, j.K)] = len(order)
-            order.append(g.Code(j.N, w.polar_code(j.N, j.K).h_rows))
-        idx.append(codes[(j.N, j.K)])
-    lens = [len(j.rx) for j in jobs]
-    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
-    rx = torch.from_numpy(np.concatenate([j.rx for j in jobs])).cuda()
-    plan = g.BatchPlan(order, np.array(idx, np.uint32), [j.M for j in jobs],
-                       [j.cap for j in jobs], [j.noise_var for j in jobs], offs, rx)
-    return plan, order
-
-
-def outputs(plan):
-    o = plan.out
-    return [t.cpu().numpy().copy() for t in (o.codewords, o.queries, o.abandoned, o.status,
-                                              o.checks)]
 
 
 def clear(plan):
