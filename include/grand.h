@@ -282,6 +282,13 @@ int grand_plain_run_trace(const grand_code *const *codes, uint32_t n_codes,
                           const grand_trace_req *reqs, uint32_t count, const float *rx,
                           grand_result *results, double *wall_s);
 
+/* Test hook for callers that exercise failure handling: the next `count`
+ * server launches (process-wide) fail as if the launch call had failed.  Each
+ * such launch returns its requests as results with status GRAND_EDEVICE, and
+ * the grand_server_poll call that attempted it returns GRAND_EDEVICE; the
+ * server stays usable.  0 disarms it. */
+void grand_debug_fail_launches(uint32_t count);
+
 #ifdef __cplusplus
 }
 #endif

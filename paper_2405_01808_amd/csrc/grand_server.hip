@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -50,6 +51,8 @@ struct Request {
 };
 
 constexpr uint32_t kSlotFloats = kMaxItems;   // 2L <= N <= 1024 received values
+
+std::atomic<uint32_t> g_fail_launches{0};     // test hook: launches to fail
 
 struct Lane {
     hipStream_t stream = nullptr;
@@ -244,7 +247,11 @@ int lane_launch(grand_server *s, Lane &L)
     L.taken.assign(B, 0);
     L.left = B;
     s->running += B;
-    int rc = launch_decode(a, grid, t.block, L.stream) ? GRAND_EDEVICE : GRAND_OK;
+    uint32_t inject = g_fail_launches.load();
+    while (inject && !g_fail_launches.compare_exchange_weak(inject, inject - 1)) {
+    }
+    int rc = inject ? GRAND_EDEVICE
+                    : (launch_decode(a, grid, t.block, L.stream) ? GRAND_EDEVICE : GRAND_OK);
     if (rc == GRAND_OK) {
         L.res.qnext[0] += B + grid;
         if (hipEventRecord(L.done, L.stream) != hipSuccess)
@@ -367,6 +374,8 @@ int poll_locked(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *
 }  // namespace
 
 extern "C" {
+
+void grand_debug_fail_launches(uint32_t count) { g_fail_launches.store(count); }
 
 uint64_t grand_request_bytes(uint32_t n, uint32_t M)
 {

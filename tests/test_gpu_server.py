@@ -233,3 +233,30 @@ def test_persistent_destroy_with_requests_in_flight(gpu):
     j = jobs[0]
     cw, q, ab = gpu.decode(codes.order[codes.index(1024, 512)], j.rx, 4, j.noise_var, 1 << 10)
     assert q >= 1
+
+
+def test_failed_launch_returns_requests_and_server_recovers(gpu):
+    """A launch that fails (forced from the host with the test hook) returns
+    its requests as GRAND_EDEVICE results; the server then serves normally."""
+    from paper_2405_01808_amd import _native as nat
+    codes = Codes(gpu)
+    jobs = w.config_jobs("serving_mix", count=12, cap=1 << 10)
+    srv = gpu.Server(max_inflight=64, lanes=1, max_batch=64, memory_budget=1 << 30)
+    ids = [srv.submit(codes.order[codes.index(j.N, j.K)], j.rx, j.M, j.noise_var, j.cap)
+           for j in jobs[:6]]
+    nat.lib().grand_debug_fail_launches(1)
+    try:
+        with pytest.raises(gpu.GrandError):
+            srv.poll()                  # this poll's launch fails
+    finally:
+        nat.lib().grand_debug_fail_launches(0)
+    got = wait_results(srv, 6)
+    assert sorted(r.request_id for r in got) == sorted(ids)
+    assert all(r.status == nat.GRAND_EDEVICE for r in got)
+    assert srv.stats() == {"pending": 0, "running": 0, "memory_in_use": 0}
+    ids2 = [srv.submit(codes.order[codes.index(j.N, j.K)], j.rx, j.M, j.noise_var, j.cap)
+            for j in jobs[6:]]
+    got2 = sorted(wait_results(srv, 6), key=lambda r: r.request_id)
+    srv.close()
+    assert [r.request_id for r in got2] == sorted(ids2)
+    assert_equal_single(gpu, codes, jobs[6:], got2)
