@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--plain-count", type=int, default=2000)
     ap.add_argument("--latency-reps", type=int, default=100)
+    ap.add_argument("--pipeline-streams", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB three times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -238,6 +239,31 @@ def main():
     launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     log(f"timed {args.steps} steps: {wall:.3f}s wall, launch ms {launch_ms}")
 
+    # the same K steps with consecutive batches on two streams, so one
+    # batch's last words overlap the next batch's start (reported beside the
+    # headline, which keeps one launch at a time)
+    pipe = None
+    if args.pipeline_streams > 1:
+        S = args.pipeline_streams
+        pstreams = [torch.cuda.Stream(dev) for _ in range(S)]
+        pplans = [plan] + [g.BatchPlan([code], np.zeros(len(jobs), np.uint32),
+                                       [j.M for j in jobs], [j.cap for j in jobs],
+                                       [j.noise_var for j in jobs], offs, rx) for _ in range(S - 1)]
+        torch.cuda.synchronize()
+        for p, st in zip(pplans, pstreams):
+            p.launch(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            pplans[i % S].launch(pstreams[i % S])
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t1
+        ref_q = plan.out.queries.cpu().numpy()
+        pipe = {"streams": S, "steps": args.steps, "ms_per_step": pwall * 1e3 / args.steps,
+                "identical_results": bool(all(np.array_equal(p.out.queries.cpu().numpy(), ref_q)
+                                              for p in pplans))}
+        log(f"pipelined {args.steps} steps on {S} streams: {pwall:.3f}s wall")
+
     q = out.queries.cpu().numpy().view(np.uint64)
     ab = out.abandoned.cpu().numpy()
     st = out.status.cpu().numpy()
@@ -273,6 +299,8 @@ def main():
         "config": {"workload": WORKLOAD_DESC, "codewords": len(jobs), "N": 128, "K": 64,
                    "M": 16, "query_cap": 1 << 16},
         "codewords_per_s": len(jobs) * args.steps / wall,
+        "pipelined": (dict(pipe, value=sum_q * args.steps / (pipe["ms_per_step"] * args.steps / 1e3))
+                      if pipe else None),
         "performed_checks_per_s": sum_checks * args.steps / wall,
         "mean_q": sum_q / len(jobs),
         "abandon_rate": float(ab.mean()),
