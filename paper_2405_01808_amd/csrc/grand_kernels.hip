@@ -104,19 +104,29 @@ struct Nodes {
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
 
+// Inclusive prefix sum across the 64 lanes of a wave, in data-parallel
+// primitives (DPP) instead of LDS round trips: shifts by 1, 2, 4 and 8
+// within each row of 16 lanes (lanes with no source add 0), then the last
+// lane of row 0 is added to row 1, of row 2 to row 3 (row_bcast:15), and of
+// row 1 to rows 2 and 3 (row_bcast:31).
+__device__ inline uint32_t wave_incl_scan(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
 // Exclusive block-wide prefix sum of v; *total receives the sum.
 // Callers keep at least one barrier between two scans (wsum is reused).
 __device__ uint32_t block_exscan(uint32_t v, uint32_t *wsum, uint32_t *total)
 {
-    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= (uint32_t)d)
-            x += y;
-    }
-    if (lane == 63)
+    const uint32_t wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t x = wave_incl_scan(v);
+    if (lane_id() == 63)
         wsum[wid] = x;
     __syncthreads();
     uint32_t base = 0, tot = 0;
