@@ -401,18 +401,29 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nod
         bool first = true;
         while (ok && pstart < pend) {
             const uint32_t created_from = used;
+            // the parent fields of this thread's slot in the next block are
+            // loaded while the current block is processed (parents are not
+            // written during a pass, except each one's own frontier)
+            uint32_t nx_c = 0, nx_lo = 0, nx_ld = 0;
+            if (pstart + tid < pend) {
+                nx_c = nd.cost[pstart + tid];
+                nx_lo = first ? nd.cnext[pstart + tid] : nd.rl[pstart + tid];
+                nx_ld = nd.lead[pstart + tid];
+            }
             for (uint32_t c0 = pstart; c0 < pend; c0 += bs) {
                 const Stage S = stage_set(A.st, par, bs);
                 par ^= 1u;
                 const uint32_t h = c0 + tid;
-                uint32_t cnt = 0, lo = 0, ch = 0, lead = 0;
-                if (h < pend) {
-                    ch = nd.cost[h];
-                    lo = first ? nd.cnext[h] : nd.rl[h];
-                    if (lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
-                        lead = nd.lead[h];
-                        cnt = child_end(A.ikey, ibk, lo, n, kn, (int32_t)ch) - lo;
-                    }
+                uint32_t cnt = 0, lead = 0;
+                const uint32_t ch = nx_c, lo = nx_lo, ld = nx_ld;
+                if (h + bs < pend) {
+                    nx_c = nd.cost[h + bs];
+                    nx_lo = first ? nd.cnext[h + bs] : nd.rl[h + bs];
+                    nx_ld = nd.lead[h + bs];
+                }
+                if (h < pend && lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
+                    lead = ld;
+                    cnt = child_end(A.ikey, ibk, lo, n, kn, (int32_t)ch) - lo;
                 }
                 S.fa[tid] = h;
                 S.fb[tid] = lo;
@@ -529,6 +540,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         sh.cmax = 0;
     }
     __syncthreads();
+    uint32_t my_items = 0, my_cost = 0;   // at most 1024 flips of cost < 2^15
     for (uint32_t t = tid; t < nraw; t += bs) {
         const uint32_t sym = t >> 1, axis = t & 1u;
         float x = a.rx[job.rx_off + t];
@@ -558,8 +570,15 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         uint32_t p = base + (m - 1 - flip_bit);
         if (p < n_bits) {
             A.ikey[t] = (cost << 10) | p;
-            atomicAdd(&sh.nitems, 1u);
-            atomicAdd((uint32_t *)&sh.cmax, cost);
+            my_items++;
+            my_cost += cost;
+        }
+    }
+    {   // one atomic per wave for the flip count and the summed costs
+        const uint32_t wi = wave_incl_scan(my_items), wc = wave_incl_scan(my_cost);
+        if (lane_id() == 63) {
+            atomicAdd(&sh.nitems, wi);
+            atomicAdd((uint32_t *)&sh.cmax, wc);
         }
     }
     __syncthreads();
