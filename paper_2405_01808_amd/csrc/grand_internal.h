@@ -79,13 +79,15 @@ __host__ __device__ inline NodeLayout node_layout(uint32_t node_cap)
 }
 
 constexpr uint32_t kMergePer = 8;    // low-table merge outputs per thread and level
+constexpr uint32_t kBucketsPerKey = 1;  // cost buckets per sorted key
 
 // Dynamic LDS of the decode kernel, in 32-bit words: the hard word and its
 // syndrome, the ranked flips and their columns' leading words (ni each),
 // the low flips' columns, scan partials, two sets of per-slot staging of a
-// block of nodes (one slot per thread, with run owners), bucket indexes of
-// the ranked flips and of the low table, and the low table (keys, a second
-// key buffer for building it, and leading syndrome words, 2^b each).
+// block of nodes (one slot per thread, with run owners; the low table is
+// built in them before the bands start), bucket indexes of the ranked flips
+// and of the low table, and the low table (keys and leading syndrome words,
+// 2^b each).
 struct LdsLayout {
     uint32_t yhat, s0, ikey, col0, lcol, wsum, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
         ltmp, ls0, words;
@@ -101,18 +103,20 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.col0 = o;  o += ni;
     L.lcol = o;  o += kMaxLowBits * kMaxKW;
     L.wsum = o;  o += kMaxBlock / 64;
-    // two staging sets of one block each (set p at offset p * block)
+    // two staging sets of one block each (set p at offset p * block); the
+    // low table's build buffer overlays them (12 * block >= 2^low_bits, as
+    // the host keeps 2^low_bits <= kMergePer * block)
+    L.ltmp = o;
     L.foff = o;  o += 2 * block;
     L.fa = o;    o += 2 * block;
     L.fb = o;    o += 2 * block;
     L.fcost = o; o += 2 * block;
     L.flead = o; o += 2 * block;
     L.fown = o;  o += 2 * block;
-    L.iidx = o;  o += ni / 2 + 2;
-    L.lidx = o;  o += (1u << low_bits) / 2 + 2;
+    L.iidx = o;  o += kBucketsPerKey * ni + 2;
+    L.lidx = o;  o += kBucketsPerKey * (1u << low_bits) + 2;
     o = (o + 1) & ~1u;          // 8-byte alignment of the table
     L.lkey = o;  o += 1u << low_bits;
-    L.ltmp = o;  o += 1u << low_bits;
     o = (o + 3) & ~3u;          // 16-byte alignment of the leading words
     L.ls0 = o;   o += (1u << low_bits) + 8;   // padded for 8-wide reads
     L.words = o;

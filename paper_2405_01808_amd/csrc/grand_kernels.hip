@@ -620,7 +620,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             }
         }
     }
-    const uint32_t nbi = max(NI >> 1, 1u);
+    const uint32_t nbi = kBucketsPerKey * NI;
     const Buckets ibk{A.iidx, bucket_shift(n ? A.ikey[n - 1] >> 10 : 0u, nbi), nbi};
     build_buckets(A.ikey, n, 10, ibk.shift, nbi, A.iidx);
     // leading words of every rank's column, full columns of the low flips
@@ -630,14 +630,14 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         uint32_t r = i / kw, w = i % kw;
         A.lcol[i] = code.h_cols[(uint64_t)(A.ikey[r] & 1023u) * kw + w];
     }
-    if (tid == 0)
-        lkey[0] = 0;
-    __syncthreads();
-
     // ---- low table: merge A = subsets of flips < j with A + flip j -------
-    // (levels alternate between two buffers: one barrier per level)
+    // (levels alternate between two buffers, one barrier per level, starting
+    // in the one that makes the last level land in lkey)
     {
-        uint32_t *src = lkey, *dst = ltmp;
+        uint32_t *src = (b & 1) ? ltmp : lkey, *dst = (b & 1) ? lkey : ltmp;
+        if (tid == 0)
+            src[0] = 0;
+        __syncthreads();
         for (uint32_t j = 0; j < b; j++) {
             const uint32_t len = 1u << j, outn = 2 * len;
             const uint32_t add = ((A.ikey[j] >> 10) << kMaskBits) | (1u << j);
@@ -666,7 +666,6 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             src = dst;
             dst = t;
         }
-        lkey = src;
     }
     for (uint32_t i = tid; i < LB; i += bs) {
         uint32_t acc = 0;
@@ -674,7 +673,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             acc ^= A.col0[__builtin_ctz(msk)];
         ls0[i] = acc;
     }
-    const uint32_t nbl = max(LB >> 1, 1u);
+    const uint32_t nbl = kBucketsPerKey * LB;
     const Buckets lbk{A.lidx, bucket_shift(lkey[LB - 1] >> kMaskBits, nbl), nbl};
     build_buckets(lkey, LB, kMaskBits, lbk.shift, nbl, A.lidx);
     // node 0: the empty high subset
