@@ -60,6 +60,7 @@ struct Shared {
     uint32_t overflow;
     int32_t cmax;
     unsigned long long acc;
+    unsigned long long wband[kMaxBlock / 64];   // each wave's checks in the band
 };
 
 // Per-slot staging of one block of nodes (one slot per thread).
@@ -118,6 +119,16 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x)
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return x;
+}
+
+// Orders the LDS accesses of one wave's lanes around it (no workgroup
+// barrier): the compiler keeps them on their side, and the hardware runs
+// one wave's LDS operations in order.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Exclusive block-wide prefix sum of v; *total receives the sum.
@@ -732,33 +743,40 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             break;
         const Thr kt = thr_of(vt, n);
 
-        // checks: the band's ranges of a block of nodes end to end, one run
-        // of consecutive (node, entry) pairs per thread; each piece of a run
-        // that belongs to one node is a tight comparison loop
+        // checks.  Each wave takes every nw-th block of 64 nodes on its own,
+        // with no workgroup barrier until the band ends: the block's ranges
+        // are laid end to end (a wave scan) and cut into one run of
+        // consecutive (node, entry) pairs per lane; each piece of a run that
+        // belongs to one node is a tight comparison loop.
         LaneHit best{0xFFFFFFFFu, kNone, 0};
-        uint64_t band_size = 0;
         const uint32_t used = sh.used;
-        // the node fields of this thread's slot in the next block are
+        // (the wave index is uniform in a wave: readfirstlane keeps the
+        // loop's bookkeeping in scalar registers)
+        const uint32_t lane = lane_id(), nwv = bs >> 6;
+        const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+        const uint32_t wstride = nwv * 64;
+        const Stage S = Stage{A.st.foff + wid * 64, A.st.fa + wid * 64, A.st.fb + wid * 64,
+                              A.st.fcost + wid * 64, A.st.flead + wid * 64, A.st.fown + wid * 64};
+        unsigned long long wave_size = 0;
+        // the node fields of this lane's slot in the wave's next block are
         // loaded while the current block is processed
         uint32_t nx_ptr = 0, nx_cost = 0, nx_lead = 0, nx_rl = 0;
-        if (tid < used) {
-            nx_ptr = nd.ptr[tid];
-            nx_cost = nd.cost[tid];
-            nx_lead = nd.lead[tid];
-            nx_rl = nd.rl[tid];
+        if (wid * 64 + lane < used) {
+            const uint32_t h = wid * 64 + lane;
+            nx_ptr = nd.ptr[h];
+            nx_cost = nd.cost[h];
+            nx_lead = nd.lead[h];
+            nx_rl = nd.rl[h];
         }
-        uint32_t par = 0;
-        for (uint32_t c0 = 0; c0 < used; c0 += bs) {
-            const Stage S = stage_set(A.st, par, bs);
-            par ^= 1u;
-            const uint32_t h = c0 + tid;
+        for (uint32_t c0 = wid * 64; c0 < used; c0 += wstride) {
+            const uint32_t h = c0 + lane;
             uint32_t lo = nx_ptr, ch = nx_cost, lead = nx_lead, cnt = 0;
             const uint32_t rl = nx_rl;
-            if (h + bs < used) {
-                nx_ptr = nd.ptr[h + bs];
-                nx_cost = nd.cost[h + bs];
-                nx_lead = nd.lead[h + bs];
-                nx_rl = nd.rl[h + bs];
+            if (h + wstride < used) {
+                nx_ptr = nd.ptr[h + wstride];
+                nx_cost = nd.cost[h + wstride];
+                nx_lead = nd.lead[h + wstride];
+                nx_rl = nd.rl[h + wstride];
             }
             if (h < used) {
                 uint32_t hi = node_end(lkey, lbk, LB, kt, (int32_t)ch, h, rl, lo);
@@ -767,27 +785,29 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                     nd.ptr[h] = (uint16_t)hi;
                 }
             }
-            S.fa[tid] = h;
-            S.fb[tid] = lo;
-            S.fcost[tid] = ch;
-            S.flead[tid] = lead;
-            uint32_t total;
-            const uint32_t off = block_exscan(cnt, A.wsum, &total);
-            // runs of `run` entries, one per thread; the slot holding a
-            // run's first entry records itself as that run's owner
-            const uint32_t run = (total + bs - 1) / bs;
-            S.foff[tid] = off;
+            const uint32_t xs = wave_incl_scan(cnt);
+            const uint32_t off = xs - cnt;
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
+            wave_sync();   // the previous block's runs are done with the staging
+            S.fa[lane] = h;
+            S.fb[lane] = lo;
+            S.fcost[lane] = ch;
+            S.flead[lane] = lead;
+            S.foff[lane] = off;
+            // runs of `run` entries, one per lane; the slot holding a run's
+            // first entry records itself as that run's owner
+            const uint32_t run = (total + 63) >> 6;
             if (cnt) {
                 for (uint32_t t = (off + run - 1) / run; t * run < off + cnt; t++)
-                    S.fown[t] = tid;
+                    S.fown[t] = lane;
             }
-            __syncthreads();
-            band_size += total;
-            const uint32_t ncnt = min(bs, used - c0);
-            uint32_t j = tid * run;
+            wave_sync();
+            wave_size += total;
+            const uint32_t ncnt = min(64u, used - c0);
+            uint32_t j = lane * run;
             const uint32_t jend = min(total, j + run);
             if (j < jend) {
-                uint32_t k = S.fown[tid];
+                uint32_t k = S.fown[lane];
                 while (j < jend) {
                     const uint32_t kend = k + 1 < ncnt ? S.foff[k + 1] : total;
                     const uint32_t e = min(jend, kend);
@@ -820,14 +840,17 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                         k++;
                 }
             }
-            // no barrier: the next block stages into the other set, and its
-            // scan barrier keeps the block after it from reusing this one
         }
+        if (lane == 0)
+            sh.wband[wid] = wave_size;
 
         // best hit of the band across the workgroup
         if (tid == 0)
             sh.hit_cost = 0xFFFFFFFFu;
         __syncthreads();
+        uint64_t band_size = 0;
+        for (uint32_t w = 0; w < nwv; w++)
+            band_size += sh.wband[w];
         if (best.h != kNone)
             atomicMin(&sh.hit_cost, best.cost);
         __syncthreads();
