@@ -61,6 +61,7 @@ struct Shared {
     int32_t cmax;
     unsigned long long acc;
     unsigned long long wband[kMaxBlock / 64];   // each wave's checks in the band
+    uint32_t alloc;                  // node slots claimed in the current expansion
 };
 
 // Per-slot staging of one block of nodes (one slot per thread).
@@ -393,73 +394,90 @@ __device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t lo, uint32_
 // Raise the node store from "every high subset admitted by vE" to those
 // admitted by vwant.  The admitted child ranks of a parent form one
 // contiguous range; children of old parents not admitted by vE are new, and
-// so are all admitted children of new parents.  When the store would
-// overflow, the step is rolled back and the threshold gap halved.  Returns
-// the threshold reached (vE when even vE + 1 does not fit; sh.overflow is
-// then set).
+// so are all admitted children of new parents, so the store grows one
+// forest level per pass.  Within a pass each wave takes every nw-th block of
+// 64 parents on its own and claims its children's slots with one LDS atomic
+// (slot order varies from run to run; nothing computed from the store
+// depends on it).  When the store would overflow, the step is rolled back
+// and the threshold gap halved.  Returns the threshold reached (vE when even
+// vE + 1 does not fit; sh.overflow is then set).
 __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &nd,
                                 uint32_t n, uint32_t node_cap,
                                 int64_t vE, int64_t vwant)
 {
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const uint32_t wstride = bs;   // 64 parents per wave and block
+    const Stage S = Stage{A.st.foff + wid * 64, A.st.fa + wid * 64, A.st.fb + wid * 64,
+                          A.st.fcost + wid * 64, A.st.flead + wid * 64, A.st.fown + wid * 64};
     const uint32_t used0 = sh.used;
     const Thr kE = thr_of(vE, n);
     int64_t vn = vwant;
     for (;;) {
         const Thr kn = thr_of(vn, n);
-        bool ok = true;
-        uint32_t pstart = 0, pend = used0, used = used0, par = 0;
+        if (tid == 0)
+            sh.alloc = used0;
+        __syncthreads();
+        uint32_t pstart = 0, pend = used0;
         bool first = true;
-        while (ok && pstart < pend) {
-            const uint32_t created_from = used;
-            // the parent fields of this thread's slot in the next block are
-            // loaded while the current block is processed (parents are not
-            // written during a pass, except each one's own frontier)
+        for (;;) {   // one pass per forest level
+            // the parent fields of this lane's slot in the wave's next block
+            // are loaded while the current block is processed (parents are
+            // not written during a pass, except each one's own frontier)
             uint32_t nx_c = 0, nx_lo = 0, nx_ld = 0;
-            if (pstart + tid < pend) {
-                nx_c = nd.cost[pstart + tid];
-                nx_lo = first ? nd.cnext[pstart + tid] : nd.rl[pstart + tid];
-                nx_ld = nd.lead[pstart + tid];
+            {
+                const uint32_t h = pstart + wid * 64 + lane;
+                if (h < pend) {
+                    nx_c = nd.cost[h];
+                    nx_lo = first ? nd.cnext[h] : nd.rl[h];
+                    nx_ld = nd.lead[h];
+                }
             }
-            for (uint32_t c0 = pstart; c0 < pend; c0 += bs) {
-                const Stage S = stage_set(A.st, par, bs);
-                par ^= 1u;
-                const uint32_t h = c0 + tid;
+            for (uint32_t c0 = pstart + wid * 64; c0 < pend; c0 += wstride) {
+                const uint32_t h = c0 + lane;
                 uint32_t cnt = 0, lead = 0;
                 const uint32_t ch = nx_c, lo = nx_lo, ld = nx_ld;
-                if (h + bs < pend) {
-                    nx_c = nd.cost[h + bs];
-                    nx_lo = first ? nd.cnext[h + bs] : nd.rl[h + bs];
-                    nx_ld = nd.lead[h + bs];
+                if (h + wstride < pend) {
+                    nx_c = nd.cost[h + wstride];
+                    nx_lo = first ? nd.cnext[h + wstride] : nd.rl[h + wstride];
+                    nx_ld = nd.lead[h + wstride];
                 }
                 if (h < pend && lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
                     lead = ld;
                     cnt = child_end(A.ikey, ibk, lo, n, kn, (int32_t)ch) - lo;
                 }
-                S.fa[tid] = h;
-                S.fb[tid] = lo;
-                S.fcost[tid] = ch;
-                S.flead[tid] = lead;
-                uint32_t total;
-                const uint32_t off = block_exscan(cnt, A.wsum, &total);
-                if (used + total > node_cap) {
-                    ok = false;   // uniform: every thread sees the same values
-                    break;
-                }
-                S.foff[tid] = off;
-                // the slot of child j < blockDim (a thread's first child)
-                for (uint32_t j = off; j < min(off + cnt, bs); j++)
-                    S.fown[j] = tid;
+                const uint32_t xs = wave_incl_scan(cnt);
+                const uint32_t off = xs - cnt;
+                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
+                uint32_t base = 0;
+                if (lane == 0 && total)
+                    base = atomicAdd(&sh.alloc, total);
+                base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
+                // children past the capacity are not written; the pass then
+                // ends in a roll-back
+                const bool fits = (uint64_t)base + total <= node_cap;
                 if (h < pend && (cnt || !first))
                     nd.cnext[h] = (uint16_t)(lo + cnt);
-                __syncthreads();
-                const uint32_t ncnt = min(bs, pend - c0);
-                uint32_t k = tid < total ? S.fown[tid] : 0;
-                for (uint32_t j = tid; j < total; j += bs) {
-                    if (j >= bs)
+                if (!total || !fits)
+                    continue;
+                wave_sync();   // the previous block's children are written
+                S.fa[lane] = h;
+                S.fb[lane] = lo;
+                S.fcost[lane] = ch;
+                S.flead[lane] = lead;
+                S.foff[lane] = off;
+                // the slot of child j < 64 (a lane's first child)
+                for (uint32_t j = off; j < min(off + cnt, 64u); j++)
+                    S.fown[j] = lane;
+                wave_sync();
+                const uint32_t ncnt = min(64u, pend - c0);
+                uint32_t k = lane < total ? S.fown[lane] : 0;
+                for (uint32_t j = lane; j < total; j += 64) {
+                    if (j >= 64)
                         k = flat_owner(S.foff, k, ncnt, j);
-                    uint32_t r = S.fb[k] + (j - S.foff[k]);
-                    uint32_t dst = used + j;
+                    const uint32_t r = S.fb[k] + (j - S.foff[k]);
+                    const uint32_t dst = base + j;
                     nd.cost[dst] = S.fcost[k] + (A.ikey[r] >> 10);
                     nd.lead[dst] = S.flead[k] ^ A.col0[r];
                     nd.par[dst] = S.fa[k];
@@ -467,22 +485,25 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nod
                     nd.ptr[dst] = 0;
                     nd.cnext[dst] = (uint16_t)(r + 1);
                 }
-                used += total;
             }
-            // the next pass reads this pass's children as parents
+            // the pass's children are the next pass's parents
             __syncthreads();
-            pstart = created_from;
-            pend = used;
+            const uint32_t created = sh.alloc;
+            __syncthreads();   // read before the next pass claims slots
+            if (created > node_cap || created == pend)
+                break;
+            pstart = pend;
+            pend = created;
             first = false;
         }
-        if (ok) {
+        const uint32_t used = sh.alloc;
+        if (used <= node_cap) {
             if (tid == 0)
                 sh.used = used;
             __syncthreads();
             return vn;
         }
         // roll back: drop the new nodes and restore the old child frontiers
-        __syncthreads();
         for (uint32_t h = tid; h < used0; h += bs)
             nd.cnext[h] = (uint16_t)child_end(A.ikey, ibk, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
         __syncthreads();
