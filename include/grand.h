@@ -289,6 +289,18 @@ int grand_plain_run_trace(const grand_code *const *codes, uint32_t n_codes,
  * server stays usable.  0 disarms it. */
 void grand_debug_fail_launches(uint32_t count);
 
+/* Measured peak of the decode kernel's roofline: the 32-bit bitwise
+ * throughput of the current device (the incremental syndrome of Algorithm 2,
+ * Step 5, is column XORs, one v_xor_b32 per 32 syndrome bits).  Runs one
+ * warm-up and one timed launch of a probe kernel in which every lane issues
+ * `steps` x 8 dependent-free v_xor_b32 over 8 workgroups of 256 threads per
+ * compute unit, synchronously on the null stream, and stores the achieved
+ * lane-operations per second (and the timed launch's seconds, if `seconds`
+ * is not null).  `steps` must be a positive multiple of 8.  Allocates and
+ * frees a small device buffer.  Returns 0, GRAND_EINVAL for bad arguments,
+ * GRAND_ENOMEM or GRAND_EDEVICE. */
+int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds);
+
 #ifdef __cplusplus
 }
 #endif

@@ -173,3 +173,11 @@ def set_tuning(n: int, M: int, **kw):
     cur.update(kw)
     t = nat.GrandTuning(**cur)
     nat.check(nat.lib().grand_tuning_set(n, M, ctypes.byref(t)))
+
+
+def probe_xor_rate(steps: int = 1 << 14) -> tuple[float, float]:
+    """Measured 32-bit XOR lane-operations per second of the current device
+    and the timed launch's seconds (grand_probe_xor_rate)."""
+    rate, sec = ctypes.c_double(0), ctypes.c_double(0)
+    nat.check(nat.lib().grand_probe_xor_rate(int(steps), ctypes.byref(rate), ctypes.byref(sec)))
+    return rate.value, sec.value

@@ -130,3 +130,12 @@ def test_graph_calls_rejected_on_host():
     assert L.grand_graph_create(ctypes.byref(b), ctypes.byref(out)) == nat.GRAND_EINVAL
     assert L.grand_graph_launch(None, None) == nat.GRAND_EINVAL
     L.grand_graph_destroy(None)   # no-op
+
+
+def test_xor_rate_probe_rejects_bad_arguments_on_host():
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    r = ctypes.c_double()
+    assert L.grand_probe_xor_rate(0, ctypes.byref(r), None) == nat.GRAND_EINVAL
+    assert L.grand_probe_xor_rate(12, ctypes.byref(r), None) == nat.GRAND_EINVAL   # not a multiple of 8
+    assert L.grand_probe_xor_rate(8, None, None) == nat.GRAND_EINVAL
