@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
 
 class OrcJob(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("rows", ctypes.c_uint32), ("M", ctypes.c_uint32),
-                ("pad0", ctypes.c_uint32),
+                ("cutoff", ctypes.c_uint32),
                 ("h_rows", ctypes.c_void_p), ("rx", ctypes.c_void_p),
                 ("noise_var", ctypes.c_double), ("cap", ctypes.c_uint64),
                 ("codeword_out", ctypes.c_void_p), ("q_out", ctypes.c_void_p),
@@ -58,6 +58,10 @@ def lib():
         L.orc_enumerate.restype = ctypes.c_int64
         L.orc_decode.argtypes = [u32, u32, vp, vp, u32, ctypes.c_double, u64, vp, vp, vp]
         L.orc_decode.restype = ctypes.c_int
+        L.orc_decode_ex.argtypes = [u32, u32, vp, vp, u32, ctypes.c_double, u64, u32, vp, vp, vp]
+        L.orc_decode_ex.restype = ctypes.c_int
+        L.orc_select_symbols.argtypes = [u32, u32, vp, u32, vp, vp]
+        L.orc_select_symbols.restype = ctypes.c_int
         L.orc_decode_many.argtypes = [ctypes.POINTER(OrcJob), u32, u32]
         L.orc_decode_many.restype = ctypes.c_int
         _lib = L
@@ -125,7 +129,37 @@ def decode(h_rows: np.ndarray, N: int, rx: np.ndarray, M: int, noise_var: float,
     return cw, q.value, ab.value
 
 
-def decode_jobs(jobs, h_rows_of, nthreads: int | None = None, cap: int | None = None):
+def select_symbols(N: int, M: int, rx: np.ndarray, S: int):
+    """Algorithm 2 Steps 1-3: bool[L], True for the min(S, L) least reliable
+    symbols (smallest d1^2 + d2^2, ties by index)."""
+    rx = np.ascontiguousarray(rx, dtype=np.float32)
+    m = {4: 1, 16: 2, 64: 3, 256: 4, 1024: 5, 4096: 6}.get(M, 0)
+    L = (N + 2 * m - 1) // (2 * m) if m else 1
+    sel = np.zeros(L, np.uint8)
+    n = ctypes.c_uint32(0)
+    rc = lib().orc_select_symbols(N, M, _ptr(rx), int(S), _ptr(sel), ctypes.byref(n))
+    if rc != ORC_OK:
+        raise ValueError(f"orc_select_symbols failed: {rc}")
+    return sel.astype(bool)
+
+
+def decode_ex(h_rows: np.ndarray, N: int, rx: np.ndarray, M: int, noise_var: float, cap: int,
+              cutoff: int):
+    """orc_decode_ex: decode with Algorithm 2's symbol cut-off (0 = none)."""
+    h = np.ascontiguousarray(h_rows, dtype=np.uint64)
+    rx = np.ascontiguousarray(rx, dtype=np.float32)
+    cw = np.zeros((N + 63) // 64, np.uint64)
+    q = ctypes.c_uint64(0)
+    ab = ctypes.c_uint8(0)
+    rc = lib().orc_decode_ex(N, h.shape[0], _ptr(h), _ptr(rx), M, float(noise_var), int(cap),
+                             int(cutoff), _ptr(cw), ctypes.byref(q), ctypes.byref(ab))
+    if rc != ORC_OK:
+        raise ValueError(f"orc_decode_ex failed: {rc}")
+    return cw, q.value, ab.value
+
+
+def decode_jobs(jobs, h_rows_of, nthreads: int | None = None, cap: int | None = None,
+                cutoff: int = 0):
     """Decode a list of workload Jobs on a thread pool.
 
     h_rows_of(N, K) -> packed H rows.  Returns (codewords list, q array,
@@ -145,6 +179,7 @@ def decode_jobs(jobs, h_rows_of, nthreads: int | None = None, cap: int | None = 
         a.h_rows, a.rx = h.ctypes.data, rx.ctypes.data
         a.noise_var = float(j.noise_var)
         a.cap = int(j.cap if cap is None else cap)
+        a.cutoff = int(cutoff)
         a.codeword_out = cw.ctypes.data
         a.q_out = outs_q.ctypes.data + 8 * i
         a.abandoned_out = outs_ab.ctypes.data + i

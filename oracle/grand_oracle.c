@@ -372,12 +372,80 @@ int64_t orc_enumerate(uint32_t n, const uint32_t *cost_sorted, uint64_t count,
 }
 
 /* ------------------------------------------------------------------ */
+/* Symbol cut-off: Algorithm 2 Steps 1-3.                              */
+/* ------------------------------------------------------------------ */
+
+int orc_select_symbols(uint32_t N, uint32_t M, const float *rx, uint32_t S,
+                       uint8_t *selected, uint32_t *n_selected)
+{
+    int m = bits_per_axis(M);
+    if (!m || !valid_n(N) || !rx || !selected || !n_selected || S == 0)
+        return ORC_EINVAL;
+    int levels = 1 << m;
+    uint32_t L = (N + 2 * m - 1) / (2 * m);
+    uint64_t *lk = (uint64_t *)malloc(L * sizeof(uint64_t));
+    uint32_t *order = (uint32_t *)malloc(L * sizeof(uint32_t));
+    if (!lk || !order) {
+        free(lk);
+        free(order);
+        return ORC_ENOMEM;
+    }
+    /* Step 1: the symbol's reliability L(r, s) = sqrt(d1^2 + d2^2) from
+     * Definition 3.1, where d1 and d2 are the two axes' near-neighbour costs
+     * (pad bits do not change them).  The square root is monotone, so the
+     * integer d1^2 + d2^2 orders the symbols the same way. */
+    for (uint32_t i = 0; i < L; i++) {
+        uint32_t c[2];
+        for (int axis = 0; axis < 2; axis++) {
+            float x = rx[2 * i + axis];
+            if (!isfinite(x) || fabsf(x) > 32768.0f) {
+                free(lk);
+                free(order);
+                return ORC_EINVAL;
+            }
+            int idx, nbr;
+            demap_axis(x, levels, &idx, &nbr, &c[axis]);
+        }
+        lk[i] = (uint64_t)c[0] * c[0] + (uint64_t)c[1] * c[1];
+    }
+    /* Step 2: pSort ascending (ties by symbol index: insertion sort is
+     * stable).  Step 3: keep the first S symbols, the least reliable. */
+    for (uint32_t i = 0; i < L; i++) {
+        uint32_t k = i;
+        order[k] = i;
+        while (k > 0 && lk[order[k - 1]] > lk[order[k]]) {
+            uint32_t t = order[k - 1];
+            order[k - 1] = order[k];
+            order[k] = t;
+            k--;
+        }
+    }
+    uint32_t keep = S < L ? S : L;
+    memset(selected, 0, L);
+    for (uint32_t r = 0; r < keep; r++)
+        selected[order[r]] = 1;
+    *n_selected = keep;
+    free(lk);
+    free(order);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Decode: Algorithm 2.                                                */
 /* ------------------------------------------------------------------ */
 
 int orc_decode(uint32_t N, uint32_t rows, const uint64_t *h_rows,
                const float *rx, uint32_t M, double noise_var, uint64_t cap,
                uint64_t *codeword_out, uint64_t *q_out, uint8_t *abandoned_out)
+{
+    return orc_decode_ex(N, rows, h_rows, rx, M, noise_var, cap, 0, codeword_out, q_out,
+                         abandoned_out);
+}
+
+int orc_decode_ex(uint32_t N, uint32_t rows, const uint64_t *h_rows,
+                  const float *rx, uint32_t M, double noise_var, uint64_t cap,
+                  uint32_t cutoff, uint64_t *codeword_out, uint64_t *q_out,
+                  uint8_t *abandoned_out)
 {
     int m = bits_per_axis(M);
     if (!m || !valid_n(N) || rows == 0 || rows >= N || !h_rows || !rx ||
@@ -404,16 +472,33 @@ int orc_decode(uint32_t N, uint32_t rows, const uint64_t *h_rows,
     uint64_t *col = (uint64_t *)calloc((size_t)2 * L * kw, sizeof(uint64_t));
     uint64_t *syn0 = (uint64_t *)calloc(kw, sizeof(uint64_t));
     uint64_t *syn = (uint64_t *)calloc(kw, sizeof(uint64_t));
+    uint8_t *sel = (uint8_t *)calloc(L, 1);
     tep_search s;
     memset(&s, 0, sizeof(s));
     if (!yhat || !icost || !ipos || !order || !cost_sorted || !H || !s0 ||
-        !col || !syn0 || !syn)
+        !col || !syn0 || !syn || !sel)
         goto out;
 
     uint32_t n = 0;
     rc = orc_demap(N, M, rx, yhat, icost, ipos, &n);
     if (rc != ORC_OK)
         goto out;
+    if (cutoff) {
+        /* Algorithm 2 Steps 1-3: only the items of the S least reliable
+         * symbols take part; Step 4's pattern set is then all their
+         * combinations (4^S, fewer when pad bits drop items). */
+        uint32_t kept = 0, nsel = 0;
+        rc = orc_select_symbols(N, M, rx, cutoff, sel, &nsel);
+        if (rc != ORC_OK)
+            goto out;
+        for (uint32_t i = 0; i < n; i++)
+            if (sel[ipos[i] / (2u * (uint32_t)m)]) {
+                icost[kept] = icost[i];
+                ipos[kept] = ipos[i];
+                kept++;
+            }
+        n = kept;
+    }
 
     /* Algorithm 2 Step 2 (reading): rank the items by (cost, position);
      * insertion sort, n <= 2L <= 2048. */
@@ -512,6 +597,7 @@ out:
     free(col);
     free(syn0);
     free(syn);
+    free(sel);
     return rc;
 }
 
@@ -544,8 +630,9 @@ static void *pool_worker(void *arg)
             break;
         orc_job *j = &ps->jobs[i];
         double t0 = now_s();
-        j->status = orc_decode(j->N, j->rows, j->h_rows, j->rx, j->M, j->noise_var,
-                               j->cap, j->codeword_out, j->q_out, j->abandoned_out);
+        j->status = orc_decode_ex(j->N, j->rows, j->h_rows, j->rx, j->M, j->noise_var,
+                                  j->cap, j->cutoff, j->codeword_out, j->q_out,
+                                  j->abandoned_out);
         j->seconds = now_s() - t0;
     }
     return NULL;

@@ -10,8 +10,10 @@
  * Parity is pinned for: code-construction checks (Definition "Polar codes"),
  * Algorithm 1 (Theorem 3.1, Table II at N = 128), demapping (Definitions 3.1
  * and 3.2 against brute-force Euclidean geometry), the TEP order (brute-force
- * sort of all subsets, Corollary 3.1 count) and decoding (brute-force search
- * over all codewords for N <= 16).  The Gray labelling convention and the
+ * sort of all subsets, Corollary 3.1 count), decoding (brute-force search
+ * over all codewords for N <= 16) and Algorithm 2's symbol cut-off (the
+ * selection against the geometric corner distance of Definition 3.1, the
+ * decode against brute force over the selected symbols' candidates).  The Gray labelling convention and the
  * Q.12 quantisation are conventions the paper does not fix (parity unpinned
  * by the paper; pinned only by the Gray-adjacency and round-trip checks).
  */
@@ -68,8 +70,27 @@ int orc_decode(uint32_t N, uint32_t rows, const uint64_t *h_rows,
                const float *rx, uint32_t M, double noise_var, uint64_t cap,
                uint64_t *codeword_out, uint64_t *q_out, uint8_t *abandoned_out);
 
+/* Algorithm 2 Steps 1-3: rank the L symbols by L(r, s) of Definition 3.1
+ * (compared as d1^2 + d2^2 of the two axes' near-neighbour costs, ties by
+ * symbol index) and mark the first min(S, L), the least reliable, in
+ * selected[0 .. L-1] (0/1 bytes).  *n_selected receives min(S, L).
+ * Returns ORC_OK, ORC_EINVAL (S = 0 or bad arguments) or ORC_ENOMEM. */
+int orc_select_symbols(uint32_t N, uint32_t M, const float *rx, uint32_t S,
+                       uint8_t *selected, uint32_t *n_selected);
+
+/* orc_decode with Algorithm 2's cut-off: with cutoff = S > 0 only the items
+ * of the symbols orc_select_symbols marks take part, so the patterns are the
+ * 4^S combinations of those symbols' candidates (fewer when pad bits drop
+ * items) in the same order, and abandonment returns q = min(cap, 2^n) over
+ * the kept items.  cutoff = 0 is orc_decode. */
+int orc_decode_ex(uint32_t N, uint32_t rows, const uint64_t *h_rows,
+                  const float *rx, uint32_t M, double noise_var, uint64_t cap,
+                  uint32_t cutoff, uint64_t *codeword_out, uint64_t *q_out,
+                  uint8_t *abandoned_out);
+
 typedef struct {
-    uint32_t N, rows, M, pad0;
+    uint32_t N, rows, M;
+    uint32_t cutoff;           /* 0: full pattern space; S > 0: Algorithm 2 cut-off */
     const uint64_t *h_rows;
     const float *rx;
     double noise_var;
