@@ -104,6 +104,20 @@ int grand_decode(const grand_code *code, const float *rx, uint32_t M,
                  float noise_var, uint64_t query_cap, uint64_t *codeword_out,
                  uint64_t *queries_out, uint8_t *abandoned_out);
 
+/* grand_decode with Algorithm 2's symbol cut-off (Steps 1-3 and Section IV,
+ * where S = 8).  The L symbols are ranked by Definition 3.1's reliability
+ * L(r, s) = sqrt(d1^2 + d2^2) (compared as d1^2 + d2^2 of the two axes'
+ * near-neighbour costs, ties by symbol index), and only the flips of the
+ * first min(S, L) -- the least reliable -- take part: the patterns are the
+ * 4^S combinations of their candidates (fewer when pad bits drop flips), in
+ * the same order as grand_decode, and a search that finds no codeword
+ * abandons with q = min(query_cap, 2^n) over the kept flips.
+ * cutoff_symbols = 0, or >= L, is grand_decode.  Same arguments, ownership
+ * and errors as grand_decode. */
+int grand_decode_ex(const grand_code *code, const float *rx, uint32_t M,
+                    float noise_var, uint64_t query_cap, uint32_t cutoff_symbols,
+                    uint64_t *codeword_out, uint64_t *queries_out, uint8_t *abandoned_out);
+
 /* ------------------------------------------------------------------ */
 /* Many decodes, device buffers, asynchronous on a HIP stream.         */
 /* ------------------------------------------------------------------ */
@@ -128,6 +142,11 @@ typedef struct {
                                       or GRAND_ECAPACITY; may be NULL */
     uint64_t *checks_out;          /* device [count]: syndrome checks actually performed
                                       (>= q; includes speculative checks); may be NULL */
+    uint32_t cutoff_symbols;       /* Algorithm 2's cut-off S for every word: 0 searches the
+                                      full pattern space; S > 0 keeps only the flips of the
+                                      S least reliable symbols (Steps 1-3), as in
+                                      grand_decode_ex */
+    uint32_t reserved;             /* must be 0 */
 } grand_batch;
 
 /* Enqueue the decode of every codeword of the batch on `stream` (a

@@ -24,7 +24,7 @@ SERVE_PERSISTENT = 1
 EXPORTS = [
     "grand_strerror", "grand_last_error", "grand_init",
     "grand_code_create", "grand_code_destroy", "grand_code_n", "grand_code_rows",
-    "grand_decode", "grand_decode_batch", "grand_tuning_get", "grand_tuning_set",
+    "grand_decode", "grand_decode_ex", "grand_decode_batch", "grand_tuning_get", "grand_tuning_set",
     "grand_request_bytes", "grand_server_create", "grand_server_destroy", "grand_server_submit",
     "grand_server_cancel", "grand_server_poll", "grand_server_stats", "grand_server_run_trace",
     "grand_plain_run_trace", "grand_graph_create", "grand_graph_launch", "grand_graph_destroy",
@@ -46,7 +46,8 @@ class GrandBatch(ctypes.Structure):
                 ("rx_offset", ctypes.c_void_p), ("rx", ctypes.c_void_p),
                 ("codeword_out", ctypes.c_void_p), ("queries_out", ctypes.c_void_p),
                 ("abandoned_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
-                ("checks_out", ctypes.c_void_p)]
+                ("checks_out", ctypes.c_void_p),
+                ("cutoff_symbols", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class GrandServerConfig(ctypes.Structure):
@@ -105,6 +106,8 @@ def lib():
     L.grand_code_rows.restype = u32
     L.grand_decode.argtypes = [vp, vp, u32, ctypes.c_float, u64, vp, vp, vp]
     L.grand_decode.restype = i32
+    L.grand_decode_ex.argtypes = [vp, vp, u32, ctypes.c_float, u64, u32, vp, vp, vp]
+    L.grand_decode_ex.restype = i32
     L.grand_decode_batch.argtypes = [ctypes.POINTER(GrandBatch), vp]
     L.grand_decode_batch.restype = i32
     L.grand_graph_create.argtypes = [ctypes.POINTER(GrandBatch), ctypes.POINTER(vp)]

@@ -283,6 +283,8 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
     if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
         !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
         return fail(GRAND_EINVAL, "null pointer in batch");
+    if (b->reserved != 0)
+        return fail(GRAND_EINVAL, "reserved batch field must be 0");
     if (b->n_codes == 0)
         return fail(GRAND_EINVAL, "no codes");
     for (uint32_t c = 0; c < b->n_codes; c++)
@@ -361,7 +363,8 @@ void fill_tables(const grand_batch *b, const std::vector<Bucket> &buckets, DevJo
     for (auto &bk : buckets) {
         job_base.push_back(k);
         for (uint32_t i : bk.words)
-            jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i], i, 0};
+            jobs[k++] = DevJob{b->code_index[i], b->M[i], b->rx_offset[i], b->query_cap[i], i,
+                               b->cutoff_symbols};
     }
 }
 
@@ -528,6 +531,14 @@ int grand_decode(const grand_code *code, const float *rx, uint32_t M, float nois
                  uint64_t query_cap, uint64_t *codeword_out, uint64_t *queries_out,
                  uint8_t *abandoned_out)
 {
+    return grand_decode_ex(code, rx, M, noise_var, query_cap, 0, codeword_out, queries_out,
+                           abandoned_out);
+}
+
+int grand_decode_ex(const grand_code *code, const float *rx, uint32_t M, float noise_var,
+                    uint64_t query_cap, uint32_t cutoff_symbols, uint64_t *codeword_out,
+                    uint64_t *queries_out, uint8_t *abandoned_out)
+{
     if (!code || !rx || !codeword_out || !queries_out || !abandoned_out)
         return fail(GRAND_EINVAL, "null pointer");
     if (!valid_m(M))
@@ -567,7 +578,7 @@ int grand_decode(const grand_code *code, const float *rx, uint32_t M, float nois
         return rc;
     r->h_codes[0] = DevCode{code->n, code->rows, code->kw, code->row_w32, code->d_rows,
                             code->d_cols};
-    r->h_jobs[0] = DevJob{0, M, 0, query_cap, 0, 0};
+    r->h_jobs[0] = DevJob{0, M, 0, query_cap, 0, cutoff_symbols};
     std::memcpy(r->h_rx, rx, 2 * L * sizeof(float));
     HIP_TRY(hipMemcpyAsync(r->codes, r->h_codes, sizeof(DevCode), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(r->jobs, r->h_jobs, sizeof(DevJob), hipMemcpyHostToDevice, st));

@@ -32,7 +32,7 @@ struct DevJob {
     uint64_t rx_off;     // float offset of the word's 2L received values
     uint64_t cap;        // query cap
     uint32_t out;        // output slot (codeword at out * kCwStride)
-    uint32_t pad;
+    uint32_t cutoff;     // Algorithm 2's cut-off S (0: the full pattern space)
 };
 
 struct KernelArgs {

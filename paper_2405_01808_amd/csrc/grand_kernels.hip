@@ -573,6 +573,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     }
     __syncthreads();
     uint32_t my_items = 0, my_cost = 0;   // at most 1024 flips of cost < 2^15
+    const uint32_t cut = job.cutoff < L ? job.cutoff : 0u;   // Algorithm 2's S (0: none)
     for (uint32_t t = tid; t < nraw; t += bs) {
         const uint32_t sym = t >> 1, axis = t & 1u;
         float x = a.rx[job.rx_off + t];
@@ -605,6 +606,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             my_items++;
             my_cost += cost;
         }
+        if (cut)
+            A.col0[t] = cost;   // both axes, pad bits or not (col0 is free until Step 2)
     }
     {   // one atomic per wave for the flip count and the summed costs
         const uint32_t wi = wave_incl_scan(my_items), wc = wave_incl_scan(my_cost);
@@ -619,6 +622,48 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         if (tid == 0 && a.status_out)
             a.status_out[out_slot] = -1;   // GRAND_EINVAL
         return out_slot;
+    }
+    // ---- Algorithm 2 Steps 1-3 (cut-off): only the flips of the S least
+    // reliable symbols take part.  A symbol's reliability is Definition
+    // 3.1's L = sqrt(d1^2 + d2^2), compared as d1^2 + d2^2 of its two axes'
+    // costs; ties go to the lower symbol index. ------------------------------
+    if (cut) {
+        for (uint32_t i = tid; i < L; i += bs) {
+            const uint32_t c0 = A.col0[2 * i], c1 = A.col0[2 * i + 1];
+            ltmp[i] = c0 * c0 + c1 * c1;   // < 2^31
+        }
+        if (tid == 0) {
+            sh.nitems = 0;
+            sh.cmax = 0;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < L; i += bs) {
+            const uint32_t li = ltmp[i];
+            uint32_t r = 0;
+            for (uint32_t j = 0; j < L; j++) {
+                const uint32_t lj = ltmp[j];
+                r += lj < li || (lj == li && j < i);
+            }
+            if (r >= cut) {
+                A.ikey[2 * i] = 0xFFFFFFFFu;
+                A.ikey[2 * i + 1] = 0xFFFFFFFFu;
+            }
+        }
+        __syncthreads();
+        uint32_t ki = 0, kc = 0;
+        for (uint32_t t = tid; t < nraw; t += bs) {
+            const uint32_t k = A.ikey[t];
+            if (k != 0xFFFFFFFFu) {
+                ki++;
+                kc += k >> 10;
+            }
+        }
+        const uint32_t wi = wave_incl_scan(ki), wc = wave_incl_scan(kc);
+        if (lane_id() == 63) {
+            atomicAdd(&sh.nitems, wi);
+            atomicAdd((uint32_t *)&sh.cmax, wc);
+        }
+        __syncthreads();
     }
     // ---- Step 2: rank the flips --------------------------------------
     if (NI <= 256 && NI <= 2 * bs)

@@ -50,16 +50,18 @@ def init(device: int = 0):
     nat.check(nat.lib().grand_init(device))
 
 
-def decode(code: Code, rx, M: int, noise_var: float, cap: int):
-    """One decode with host buffers (synchronous).
+def decode(code: Code, rx, M: int, noise_var: float, cap: int, cutoff: int = 0):
+    """One decode with host buffers (synchronous); cutoff > 0 applies
+    Algorithm 2's symbol cut-off S (grand_decode_ex).
 
     Returns (codeword uint64[ceil(n/64)], queries, abandoned)."""
     r = np.ascontiguousarray(np.asarray(rx, dtype=np.float32))
     cw = np.zeros((code.n + 63) // 64, np.uint64)
     q = ctypes.c_uint64(0)
     ab = ctypes.c_uint8(0)
-    nat.check(nat.lib().grand_decode(code.handle, _ptr(r), int(M), float(noise_var), int(cap),
-                                     _ptr(cw), ctypes.byref(q), ctypes.byref(ab)))
+    nat.check(nat.lib().grand_decode_ex(code.handle, _ptr(r), int(M), float(noise_var), int(cap),
+                                        int(cutoff), _ptr(cw), ctypes.byref(q),
+                                        ctypes.byref(ab)))
     return cw, q.value, ab.value
 
 
@@ -75,7 +77,8 @@ class BatchResult:
 class BatchPlan:
     """Host metadata and device outputs of a batch, reusable across calls."""
 
-    def __init__(self, codes, code_index, M, cap, noise_var, rx_offset, rx, device=None):
+    def __init__(self, codes, code_index, M, cap, noise_var, rx_offset, rx, device=None,
+                 cutoff: int = 0):
         import torch
         self.codes = list(codes)
         self.count = len(code_index)
@@ -112,6 +115,7 @@ class BatchPlan:
         b.abandoned_out = self.out.abandoned.data_ptr()
         b.status_out = self.out.status.data_ptr()
         b.checks_out = self.out.checks.data_ptr()
+        b.cutoff_symbols = int(cutoff)
         self.desc = b
 
     def launch(self, stream=None):
@@ -154,9 +158,11 @@ class BatchGraph:
             pass
 
 
-def decode_batch(codes, code_index, M, cap, noise_var, rx_offset, rx, stream=None) -> BatchResult:
-    """Decode many codewords on the GPU (asynchronous on `stream`)."""
-    plan = BatchPlan(codes, code_index, M, cap, noise_var, rx_offset, rx)
+def decode_batch(codes, code_index, M, cap, noise_var, rx_offset, rx, stream=None,
+                 cutoff: int = 0) -> BatchResult:
+    """Decode many codewords on the GPU (asynchronous on `stream`); cutoff > 0
+    applies Algorithm 2's symbol cut-off S to every word."""
+    plan = BatchPlan(codes, code_index, M, cap, noise_var, rx_offset, rx, cutoff=cutoff)
     out = plan.launch(stream)
     out._plan = plan   # keep host metadata alive until the caller synchronises
     return out

@@ -11,9 +11,10 @@ def h_rows(N, K):
     return w.polar_code(N, K).h_rows
 
 
-def oracle_results(jobs, nthreads=None, cap=None):
+def oracle_results(jobs, nthreads=None, cap=None, cutoff=0):
     import oracle
-    cws, q, ab, secs, used, wall = oracle.decode_jobs(jobs, h_rows, nthreads=nthreads, cap=cap)
+    cws, q, ab, secs, used, wall = oracle.decode_jobs(jobs, h_rows, nthreads=nthreads, cap=cap,
+                                                      cutoff=cutoff)
     return cws, q, ab
 
 
@@ -33,7 +34,7 @@ class GpuCodes:
         return self.codes[key][0]
 
 
-def gpu_batch(jobs, codes: GpuCodes | None = None, cap=None, stream=None):
+def gpu_batch(jobs, codes: GpuCodes | None = None, cap=None, stream=None, cutoff=0):
     """Decode jobs in one grand_decode_batch call; returns numpy arrays
     (codewords [count, 16] uint64, q uint64, abandoned uint8, status int32,
     checks uint64)."""
@@ -52,7 +53,7 @@ def gpu_batch(jobs, codes: GpuCodes | None = None, cap=None, stream=None):
     caps = np.array([j.cap if cap is None else cap for j in jobs], np.uint64)
     nv = np.array([j.noise_var for j in jobs], np.float32)
     Ms = np.array([j.M for j in jobs], np.uint32)
-    plan = g.BatchPlan(codes.order, idx, Ms, caps, nv, offs, rx)
+    plan = g.BatchPlan(codes.order, idx, Ms, caps, nv, offs, rx, cutoff=cutoff)
     out = plan.launch(stream)
     torch.cuda.synchronize()
     return (out.codewords.cpu().numpy().view(np.uint64), out.queries.cpu().numpy().view(np.uint64),

@@ -36,6 +36,8 @@ int main()
     uint64_t cw[16], q;
     uint8_t ab;
     EXPECT(grand_decode(nullptr, rx, 4, 1.0f, 10, cw, &q, &ab) == GRAND_EINVAL);
+    EXPECT(grand_decode_ex(nullptr, rx, 4, 1.0f, 10, 8, cw, &q, &ab) == GRAND_EINVAL);
+    EXPECT(grand_probe_xor_rate(0, nullptr, nullptr) == GRAND_EINVAL);
 
     grand_batch b;
     std::memset(&b, 0, sizeof(b));

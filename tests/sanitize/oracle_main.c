@@ -57,7 +57,18 @@ int main(void)
                     fails++;
                 if (q < 1 || q > 200)
                     fails++;
+                /* Algorithm 2's cut-off: selection and the restricted decode */
+                uint8_t sel[512];
+                uint32_t nsel = 0;
+                const uint32_t S = 1 + (uint32_t)trial % 4;
+                if (orc_select_symbols(N, M, rx, S, sel, &nsel) != ORC_OK || nsel != (S < L ? S : L))
+                    fails++;
+                if (orc_decode_ex(N, rows, h, rx, M, 0.5, 1u << 20, S, cw, &q, &ab) != ORC_OK ||
+                    q < 1 || q > (1ull << (2 * S)))
+                    fails++;
             }
+            if (orc_select_symbols(N, M, rx, 0, NULL, NULL) == ORC_OK)
+                fails++;
             /* error paths */
             if (orc_decode(N, rows, h, rx, 8, 0.5, 10, cw, &q, &ab) == ORC_OK)
                 fails++;

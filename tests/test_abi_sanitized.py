@@ -21,8 +21,8 @@ def test_abi_host_paths_clean_under_asan_and_ubsan(tmp_path):
            "-Xarch_host", "-fsanitize=undefined",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    cmd += [os.path.join(CSRC, f) for f in ("grand_kernels.hip", "grand_api.hip",
-                                             "grand_server.hip")]
+    from paper_2405_01808_amd.build import SOURCES   # every source of the library
+    cmd += [os.path.join(CSRC, f) for f in SOURCES]
     cmd += [os.path.join(HERE, "sanitize", "abi_main.cpp"), "-o", exe]
     build = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
     assert build.returncode == 0, build.stderr[-3000:]
