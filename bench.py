@@ -175,6 +175,52 @@ def latency(g, w, reps: int):
             "mean_q": float(np.mean(qs)), "abandon_rate": float(np.mean(abs_))}
 
 
+def cutoff_mode(g, w, jobs, code, rx, offs, S: int, reps: int = 5):
+    """Algorithm 2 with its symbol cut-off S (Section IV uses S = 8) on the
+    same batch: throughput of the batched launch, and the device time of one
+    codeword alone beside Proposition 3.1's 2n + 2S + 4 cycle bound (which
+    assumes 4^S parallel pMult circuits)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    plan = g.BatchPlan([code], np.zeros(len(jobs), np.uint32), [j.M for j in jobs],
+                       [j.cap for j in jobs], [j.noise_var for j in jobs], offs, rx, cutoff=S)
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        out = plan.launch(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    q = out.queries.cpu().numpy().view(np.uint64).astype(np.float64)
+    ab = out.abandoned.cpu().numpy()
+    chk = out.checks.cpu().numpy().view(np.uint64).astype(np.float64)
+    single = []
+    L2 = len(jobs[0].rx)
+    for i in range(min(50, len(jobs))):
+        one = g.BatchPlan([code], np.zeros(1, np.uint32), [jobs[i].M], [jobs[i].cap],
+                          [jobs[i].noise_var], np.zeros(1, np.uint64),
+                          rx[i * L2:(i + 1) * L2].contiguous(), cutoff=S)
+        one.launch(stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        one.launch(stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        single.append(a.elapsed_time(b))
+    n = int(np.log2(jobs[0].N))
+    p50 = float(np.percentile(single, 50))
+    return {"S": S, "ms_per_launch": ms, "codewords_per_s": len(jobs) / (ms / 1e3),
+            "useful_checks_per_s": q.sum() / (ms / 1e3),
+            "performed_checks_per_s": chk.sum() / (ms / 1e3), "mean_q": float(q.mean()),
+            "abandon_rate": float(ab.mean()), "single_codeword_device_p50_us": p50 * 1e3,
+            "single_codeword_cycles_p50_at_2.4GHz": p50 * 1e-3 * 2.4e9,
+            "paper_cycle_bound_2n_2S_4": 2 * n + 2 * S + 4}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +232,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--plain-count", type=int, default=2000)
     ap.add_argument("--latency-reps", type=int, default=100)
+    ap.add_argument("--cutoff", type=int, default=8,
+                    help="also time Algorithm 2 with this symbol cut-off S (0: skip)")
     ap.add_argument("--pipeline-streams", type=int, default=2)
     ap.add_argument("--no-xor-probe", dest="xor_probe", action="store_false",
                     help="skip the measured bitwise peak (grand_probe_xor_rate)")
@@ -327,6 +375,10 @@ def main():
         t0 = time.time()
         result["serving"] = serving(g, w, args.serve_count, args.plain_count)
         log(f"serving replay done in {time.time() - t0:.1f}s")
+    if args.cutoff:
+        t0 = time.time()
+        result["alg2_cutoff"] = cutoff_mode(g, w, jobs, code, rx, offs, args.cutoff)
+        log(f"cut-off mode done in {time.time() - t0:.1f}s")
     if args.latency_reps:
         t0 = time.time()
         result["latency"] = latency(g, w, args.latency_reps)
