@@ -221,6 +221,57 @@ def cutoff_mode(g, w, jobs, code, rx, offs, S: int, reps: int = 5):
             "paper_cycle_bound_2n_2S_4": 2 * n + 2 * S + 4}
 
 
+# Eb/N0 grids (dB, energy per coded bit) where each order's BLER falls.
+SWEEP_EBN0 = {M: tuple(lo + 2 * k for k in range(7))
+              for M, lo in ((4, 0), (16, 4), (64, 8), (256, 12), (1024, 16), (4096, 20))}
+SWEEP_CHUNK = 25000   # codewords per launch (bounds host and device memory)
+
+
+def bler_sweep(g, w, trials: int, S: int):
+    """BLER and abandon rate of Algorithm 2 with cut-off S over N = 32..1024
+    and M = 4..4096 (the grid of Section V's Figure 4), `trials` seeded
+    codewords per point, decoded in batches on the GPU."""
+    import torch
+    rows = []
+    t0 = time.time()
+    for N in (32, 64, 128, 256, 512, 1024):
+        code_w = w.polar_code(N, N // 2)
+        code = g.Code(N, code_w.h_rows)
+        for M in (4, 16, 64, 256, 1024, 4096):
+            for ebn0 in SWEEP_EBN0[M]:
+                rng = np.random.default_rng(N * 1_000_003 + M * 101 + ebn0)
+                s2 = w.noise_variance(M, ebn0)
+                errors = abandons = 0
+                ms = 0.0
+                for c0 in range(0, trials, SWEEP_CHUNK):
+                    cnt = min(SWEEP_CHUNK, trials - c0)
+                    u = rng.integers(0, 2, (cnt, N // 2), dtype=np.uint8)
+                    c = code_w.encode(u)
+                    rx = w.awgn(w.modulate(c, M).astype(np.float64), s2, rng).reshape(cnt, -1)
+                    L2 = rx.shape[1]
+                    plan = g.BatchPlan([code], np.zeros(cnt, np.uint32), [M] * cnt,
+                                       [4 ** S] * cnt, [s2] * cnt,
+                                       np.arange(cnt, dtype=np.uint64) * L2,
+                                       torch.from_numpy(np.ascontiguousarray(rx).reshape(-1)).cuda(),
+                                       cutoff=S)
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    out = plan.launch()
+                    b.record()
+                    torch.cuda.synchronize()
+                    ms += a.elapsed_time(b)
+                    nw = (N + 63) // 64
+                    dec = out.codewords.cpu().numpy().view(np.uint64)[:, :nw]
+                    errors += int((~np.all(dec == w.pack_bits(c), axis=1)).sum())
+                    abandons += int(out.abandoned.cpu().numpy().sum())
+                rows.append({"N": N, "M": M, "ebn0_db": ebn0, "bler": errors / trials,
+                             "abandon": abandons / trials, "ms": ms})
+            log(f"sweep N={N} M={M} done ({time.time() - t0:.1f}s)")
+    return {"metric": "BLER / abandon rate", "S": S, "cap": 4 ** S, "trials_per_point": trials,
+            "ebn0": "dB per coded bit", "data": "synthetic", "points": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +283,9 @@ def main():
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--plain-count", type=int, default=2000)
     ap.add_argument("--latency-reps", type=int, default=100)
+    ap.add_argument("--bler-sweep", type=int, default=0, metavar="TRIALS",
+                    help="only run the BLER/abandon sweep with TRIALS codewords per point "
+                         "and print its JSON line")
     ap.add_argument("--cutoff", type=int, default=8,
                     help="also time Algorithm 2 with this symbol cut-off S (0: skip)")
     ap.add_argument("--pipeline-streams", type=int, default=2)
@@ -256,6 +310,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     g.init(0)
+    if args.bler_sweep:
+        print(json.dumps(bler_sweep(g, w, args.bler_sweep, args.cutoff or 8)), flush=True)
+        return
     t0 = time.time()
     jobs = w.config_jobs(WORKLOAD, count=args.count)
     log(f"generated {len(jobs)} codewords in {time.time() - t0:.1f}s")

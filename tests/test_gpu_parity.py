@@ -39,6 +39,18 @@ def test_single_decode_matches_oracle(gpu, N, M):
         assert np.array_equal(cw, ocw[i]), i
 
 
+@pytest.mark.parametrize("N,M,lo", [(32, 1024, 8.0), (128, 1024, 16.0), (256, 4096, 16.0),
+                                    (1024, 1024, 16.0), (1024, 4096, 16.0)])
+def test_high_order_qam_batches_match_oracle(gpu, N, M, lo):
+    """1024- and 4096-QAM (the paper's highest orders) at SNRs where words
+    both decode and abandon."""
+    jobs = w.jobs_from_spec(f"hiqam{N}_{M}", seed=N * 11 + M, count=48, cap=20000, Ns=(N,),
+                            Ms=(M,), ebn0=("uniform", lo, 30.0))
+    orc = oracle_results(jobs)
+    assert 0 < int(orc[2].sum()) < len(jobs), "want both hits and abandons"
+    assert_parity(jobs, gpu_batch(jobs), orc, label=f"{N}/{M}")
+
+
 def test_polar32_qpsk_full_config_single_path(gpu):
     """All 1000 codewords of the N=32 QPSK workload, one decode per call."""
     jobs = w.config_jobs("polar32_qpsk")
