@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--bler-sweep", type=int, default=0, metavar="TRIALS",
                     help="only run the BLER/abandon sweep with TRIALS codewords per point "
                          "and print its JSON line")
+    ap.add_argument("--no-dense-baseline", dest="dense_baseline", action="store_false",
+                    help="skip the dense per-pattern pMult baseline")
     ap.add_argument("--cutoff", type=int, default=8,
                     help="also time Algorithm 2 with this symbol cut-off S (0: skip)")
     ap.add_argument("--pipeline-streams", type=int, default=2)
@@ -432,6 +434,19 @@ def main():
         t0 = time.time()
         result["serving"] = serving(g, w, args.serve_count, args.plain_count)
         log(f"serving replay done in {time.time() - t0:.1f}s")
+    if args.dense_baseline:
+        t0 = time.time()
+        d128, z128 = g.probe_dense_pmult(code, len(jobs), 4096)
+        code1k = g.Code(1024, w.polar_code(1024, 512).h_rows)
+        d1k, _ = g.probe_dense_pmult(code1k, 2048, 256)
+        inc = sum_checks * args.steps / wall
+        result["dense_pmult_baseline"] = {
+            "what": "one full Algorithm 1 product per pattern (Step 5 as printed), "
+                    "grand_probe_dense_pmult",
+            "N128_checks_per_s": d128, "N1024_checks_per_s": d1k,
+            "incremental_performed_checks_per_s_N128": inc,
+            "incremental_over_dense_N128": inc / d128}
+        log(f"dense pMult baseline done in {time.time() - t0:.1f}s")
     if args.cutoff:
         t0 = time.time()
         result["alg2_cutoff"] = cutoff_mode(g, w, jobs, code, rx, offs, args.cutoff)

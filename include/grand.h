@@ -320,6 +320,22 @@ void grand_debug_fail_launches(uint32_t count);
  * GRAND_ENOMEM or GRAND_EDEVICE. */
 int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds);
 
+/* Baseline for the incremental syndrome: the paper's Step 5 model, one full
+ * Algorithm 1 product s = H (yhat + e)^T per test error pattern (bit-packed
+ * rows of `code` in LDS; per row an AND with the word, an XOR fold and a
+ * parity).  Runs `words` x `patterns` checks: word w is a hash-generated hard
+ * word (bit i of 32-bit word k is bit i of hash(w, k), with
+ * hash(a, b) = f(a * 0x9E3779B1 ^ (b + 0x7F4A7C15) * 0x85EBCA77) and
+ * f(h) = ((h ^ h >> 15) * 0x2C1B3C6D) ^ (... >> 12), bits past n cleared);
+ * pattern p flips bit j of p at position j * n / 16, j < 16.  One warm-up
+ * launch, one timed launch, synchronously on the null stream; stores the
+ * checks per second and (if not null) the number of zero syndromes found.
+ * patterns <= 65536.  Allocates and frees a small device buffer.  Returns 0,
+ * GRAND_EINVAL, GRAND_ENOMEM or GRAND_EDEVICE (also when the code lives on
+ * another device). */
+int grand_probe_dense_pmult(const grand_code *code, uint32_t words, uint32_t patterns,
+                            double *checks_per_s, uint64_t *zero_syndromes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,7 @@ EXPORTS = [
     "grand_request_bytes", "grand_server_create", "grand_server_destroy", "grand_server_submit",
     "grand_server_cancel", "grand_server_poll", "grand_server_stats", "grand_server_run_trace",
     "grand_plain_run_trace", "grand_graph_create", "grand_graph_launch", "grand_graph_destroy",
-    "grand_debug_fail_launches", "grand_probe_xor_rate",
+    "grand_debug_fail_launches", "grand_probe_xor_rate", "grand_probe_dense_pmult",
 ]
 
 
@@ -121,6 +121,9 @@ def lib():
     L.grand_probe_xor_rate.argtypes = [u32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]
     L.grand_probe_xor_rate.restype = i32
+    L.grand_probe_dense_pmult.argtypes = [vp, u32, u32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_uint64)]
+    L.grand_probe_dense_pmult.restype = i32
     L.grand_tuning_get.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]
     L.grand_tuning_get.restype = i32
     L.grand_tuning_set.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]

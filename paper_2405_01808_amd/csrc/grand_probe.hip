@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include "grand.h"
+#include "grand_host.h"
 
 namespace {
 
@@ -38,7 +39,148 @@ __global__ __launch_bounds__(256) void xor_rate_kernel(uint32_t steps, uint32_t 
     out[t] = a + b + c + d + e + f + g + h;
 }
 
+// Baseline for the incremental syndrome: Algorithm 1 run in full for every
+// pattern, as in Algorithm 2's Step 5 (one pMult per test error pattern).
+// Check g of the launch takes word g / patterns and pattern g % patterns:
+// the word is a hash-generated hard decision, the pattern flips the bits of
+// the pattern index at 16 positions spread over the word.  s = H (yhat + e)
+// is formed row by row from the bit-packed rows in LDS (AND, XOR-fold of the
+// row's words, parity), and zero syndromes are counted.  N is a template
+// parameter, so the word stays in registers and the flip positions fold.
+__device__ inline uint32_t probe_hash(uint32_t a, uint32_t b)
+{
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return h;
+}
+
+template <uint32_t N>
+__global__ __launch_bounds__(256) void dense_pmult_kernel(const uint32_t *h_rows, uint32_t rows,
+                                                          uint64_t checks, uint32_t patterns,
+                                                          unsigned long long *zeros)
+{
+    constexpr uint32_t W = N <= 64 ? 2u : N / 32u;   // 32-bit words per packed row
+    extern __shared__ uint32_t hs[];
+    for (uint32_t i = threadIdx.x; i < rows * W; i += blockDim.x)
+        hs[i] = h_rows[i];
+    __syncthreads();
+    unsigned long long found = 0;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < checks;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t wi = (uint32_t)(g / patterns), p = (uint32_t)(g % patterns);
+        uint32_t x[W];
+#pragma unroll
+        for (uint32_t k = 0; k < W; k++) {
+            const uint32_t valid = N >= 32 * (k + 1) ? 0xFFFFFFFFu
+                                   : (N <= 32 * k ? 0u : (1u << (N - 32 * k)) - 1u);
+            x[k] = probe_hash(wi, k) & valid;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < 16; j++) {
+            const uint32_t pos = j * N / 16;
+            x[pos >> 5] ^= ((p >> j) & 1u) << (pos & 31u);
+        }
+        uint32_t any = 0;
+        for (uint32_t r = 0; r < rows; r++) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < W; k++)
+                acc ^= hs[r * W + k] & x[k];
+            any |= __popc(acc) & 1u;
+        }
+        found += any == 0;
+    }
+    if (found)
+        atomicAdd(zeros, found);
+}
+
+template <uint32_t N>
+int launch_dense(const grand_code *c, uint32_t grid, uint64_t checks, uint32_t patterns,
+                 unsigned long long *zeros)
+{
+    const uint32_t lds = c->rows * c->row_w32 * 4u;
+    if (hipFuncSetAttribute((const void *)dense_pmult_kernel<N>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return GRAND_EDEVICE;
+    hipLaunchKernelGGL(dense_pmult_kernel<N>, dim3(grid), dim3(256), lds, 0, c->d_rows, c->rows,
+                       checks, patterns, zeros);
+    return hipGetLastError() == hipSuccess ? 0 : GRAND_EDEVICE;
+}
+
+int launch_dense_any(const grand_code *c, uint32_t grid, uint64_t checks, uint32_t patterns,
+                     unsigned long long *zeros)
+{
+    switch (c->n) {
+    case 2: return launch_dense<2>(c, grid, checks, patterns, zeros);
+    case 4: return launch_dense<4>(c, grid, checks, patterns, zeros);
+    case 8: return launch_dense<8>(c, grid, checks, patterns, zeros);
+    case 16: return launch_dense<16>(c, grid, checks, patterns, zeros);
+    case 32: return launch_dense<32>(c, grid, checks, patterns, zeros);
+    case 64: return launch_dense<64>(c, grid, checks, patterns, zeros);
+    case 128: return launch_dense<128>(c, grid, checks, patterns, zeros);
+    case 256: return launch_dense<256>(c, grid, checks, patterns, zeros);
+    case 512: return launch_dense<512>(c, grid, checks, patterns, zeros);
+    case 1024: return launch_dense<1024>(c, grid, checks, patterns, zeros);
+    default: return GRAND_EINVAL;
+    }
+}
+
 }  // namespace
+
+extern "C" int grand_probe_dense_pmult(const grand_code *code, uint32_t words,
+                                       uint32_t patterns, double *checks_per_s,
+                                       uint64_t *zero_syndromes)
+{
+    if (!code || !checks_per_s || words == 0 || patterns == 0 || patterns > 65536)
+        return GRAND_EINVAL;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != code->device ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return GRAND_EDEVICE;
+    const uint64_t checks = (uint64_t)words * patterns;
+    const uint32_t grid = (uint32_t)cus * 8u;
+    unsigned long long *zeros = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = GRAND_EDEVICE;
+    float ms = 0.0f;
+    unsigned long long hz = 0;
+    if (hipMalloc((void **)&zeros, sizeof(unsigned long long)) != hipSuccess)
+        return GRAND_ENOMEM;
+    if (hipMemset(zeros, 0, sizeof(unsigned long long)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        goto done;
+    // warm-up on the first word's patterns, then the timed launch
+    rc = launch_dense_any(code, grid, patterns, patterns, zeros);
+    if (rc)
+        goto done;
+    rc = GRAND_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemset(zeros, 0, sizeof(unsigned long long)) != hipSuccess ||
+        hipEventRecord(e0, 0) != hipSuccess)
+        goto done;
+    rc = launch_dense_any(code, grid, checks, patterns, zeros);
+    if (rc)
+        goto done;
+    rc = GRAND_EDEVICE;
+    if (hipEventRecord(e1, 0) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0.0f ||
+        hipMemcpy(&hz, zeros, sizeof(hz), hipMemcpyDeviceToHost) != hipSuccess)
+        goto done;
+    *checks_per_s = (double)checks / (ms * 1e-3);
+    if (zero_syndromes)
+        *zero_syndromes = hz;
+    rc = 0;
+done:
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipFree(zeros);
+    return rc;
+}
 
 extern "C" int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds)
 {

@@ -187,3 +187,13 @@ def probe_xor_rate(steps: int = 1 << 14) -> tuple[float, float]:
     rate, sec = ctypes.c_double(0), ctypes.c_double(0)
     nat.check(nat.lib().grand_probe_xor_rate(int(steps), ctypes.byref(rate), ctypes.byref(sec)))
     return rate.value, sec.value
+
+
+def probe_dense_pmult(code: Code, words: int, patterns: int) -> tuple[float, int]:
+    """Checks per second of one full Algorithm 1 product per pattern (the
+    incremental syndrome's baseline), and the zero syndromes it found
+    (grand_probe_dense_pmult)."""
+    rate, zeros = ctypes.c_double(0), ctypes.c_uint64(0)
+    nat.check(nat.lib().grand_probe_dense_pmult(code.handle, int(words), int(patterns),
+                                                ctypes.byref(rate), ctypes.byref(zeros)))
+    return rate.value, zeros.value
