@@ -221,6 +221,91 @@ def cutoff_mode(g, w, jobs, code, rx, offs, S: int, reps: int = 5):
             "paper_cycle_bound_2n_2S_4": 2 * n + 2 * S + 4}
 
 
+def plain_small(g, w):
+    """The small case: 1000 N=32 QPSK codewords (4 dB, cap 10^4), one
+    grand_decode call per codeword (host buffers in and out)."""
+    jobs = w.config_jobs("polar32_qpsk")
+    code = g.Code(32, w.polar_code(32, 16).h_rows)
+    g.decode(code, jobs[0].rx, jobs[0].M, jobs[0].noise_var, jobs[0].cap)   # warm
+    us, qs = [], []
+    t0 = time.perf_counter()
+    for j in jobs:
+        t = time.perf_counter()
+        _, q, _ = g.decode(code, j.rx, j.M, j.noise_var, j.cap)
+        us.append((time.perf_counter() - t) * 1e6)
+        qs.append(q)
+    wall = time.perf_counter() - t0
+    return {"workload": "polar32_qpsk: N=32 K=16, QPSK, 4 dB, cap 10^4, one grand_decode per "
+                        "codeword", "codewords": len(jobs), "calls_per_s": len(jobs) / wall,
+            "useful_checks_per_s": float(np.sum(qs)) / wall, "mean_q": float(np.mean(qs)),
+            "p50_us": float(np.percentile(us, 50)), "p99_us": float(np.percentile(us, 99))}
+
+
+def uneven_batch(g, w, reps: int = 5, tune: bool = True):
+    """The uneven batch (16384 words, N in {64..512}, M in {4, 16, 64}, cap
+    2^18): autotune the merged launch's tuning on a 4096-word sample, then
+    time the whole batch eagerly and as a replayed HIP graph."""
+    import torch
+    jobs = w.config_jobs("uneven_mix")
+    codes, order = {}, []
+    idx = []
+    for j in jobs:
+        if j.N not in codes:
+            codes[j.N] = len(order)
+            order.append(g.Code(j.N, w.polar_code(j.N, j.K).h_rows))
+        idx.append(codes[j.N])
+    lens = np.array([len(j.rx) for j in jobs])
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    rx = torch.from_numpy(np.concatenate([j.rx for j in jobs])).cuda()
+    idx = np.array(idx, np.uint32)
+    Ms = np.array([j.M for j in jobs], np.uint32)
+    caps = np.array([j.cap for j in jobs], np.uint64)
+    nvs = np.array([j.noise_var for j in jobs], np.float32)
+    before = g.get_tuning(0, 0)
+    tuned = None
+    stream = torch.cuda.current_stream()
+    try:
+        if tune:
+            k = 4096
+            tuned = g.autotune_batch(order, idx[:k], Ms[:k], caps[:k], nvs[:k], offs[:k], rx,
+                                     reps=2)
+        plan = g.BatchPlan(order, idx, Ms, caps, nvs, offs, rx)
+        graph = g.BatchGraph(plan)
+
+        def timed(launch):
+            launch(stream)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for a, b in ev:
+                a.record(stream)
+                launch(stream)
+                b.record(stream)
+            torch.cuda.synchronize()
+            res = [t.cpu().numpy().copy() for t in (plan.out.codewords, plan.out.queries,
+                                                     plan.out.abandoned, plan.out.status)]
+            return float(np.mean([a.elapsed_time(b) for a, b in ev])), res
+
+        eager_ms, r_eager = timed(plan.launch)
+        graph_ms, r_graph = timed(graph.launch)
+        graph.close()
+    finally:
+        g.set_tuning(0, 0, **before)
+    q = r_graph[1].view(np.uint64).astype(np.float64)
+    return {"workload": "uneven_mix: 16384 words, N in {64,128,256,512} (K=N/2), M in {4,16,64}, "
+                        "Eb/N0 ~ U[2,8] dB, cap 2^18, one merged launch",
+            "eager_ms": eager_ms, "graph_ms": graph_ms,
+            "useful_checks_per_s": q.sum() / (graph_ms / 1e3),
+            "codewords_per_s": len(jobs) / (graph_ms / 1e3), "mean_q": float(q.mean()),
+            "abandon_rate": float(r_graph[2].mean()),
+            "status_errors": int((r_graph[3] != 0).sum()),
+            "graph_equals_eager": all(np.array_equal(x, y) for x, y in zip(r_eager, r_graph)),
+            "autotuned": ({"best": tuned["best"], "sample_ms": tuned["ms"],
+                           "default_sample_ms": next((t["ms"] for t in tuned["table"]
+                                                      if t["tuning"] == before), None)}
+                          if tuned else None)}
+
+
 # Eb/N0 grids (dB, energy per coded bit) where each order's BLER falls.
 SWEEP_EBN0 = {M: tuple(lo + 2 * k for k in range(7))
               for M, lo in ((4, 0), (16, 4), (64, 8), (256, 12), (1024, 16), (4096, 20))}
@@ -286,6 +371,8 @@ def main():
     ap.add_argument("--bler-sweep", type=int, default=0, metavar="TRIALS",
                     help="only run the BLER/abandon sweep with TRIALS codewords per point "
                          "and print its JSON line")
+    ap.add_argument("--no-uneven", dest="uneven", action="store_false",
+                    help="skip the uneven (mixed-size) batch measurement")
     ap.add_argument("--no-dense-baseline", dest="dense_baseline", action="store_false",
                     help="skip the dense per-pattern pMult baseline")
     ap.add_argument("--cutoff", type=int, default=8,
@@ -434,6 +521,11 @@ def main():
         t0 = time.time()
         result["serving"] = serving(g, w, args.serve_count, args.plain_count)
         log(f"serving replay done in {time.time() - t0:.1f}s")
+    if args.uneven:
+        t0 = time.time()
+        result["plain_small"] = plain_small(g, w)
+        result["uneven_batch"] = uneven_batch(g, w)
+        log(f"uneven batch done in {time.time() - t0:.1f}s")
     if args.dense_baseline:
         t0 = time.time()
         d128, z128 = g.probe_dense_pmult(code, len(jobs), 4096)

@@ -6,4 +6,4 @@ from .decoder import (Code, BatchGraph, BatchPlan, BatchResult, decode, decode_b
                       set_tuning)
 from ._native import GrandError, CW_STRIDE, GRAND_MAX_CAP  # noqa: F401
 from .server import Server, Trace, Result, request_bytes  # noqa: F401
-from .autotune import autotune  # noqa: F401,E402
+from .autotune import autotune, autotune_batch  # noqa: F401,E402

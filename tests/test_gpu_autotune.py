@@ -54,3 +54,37 @@ def test_autotune_installs_fastest_valid_candidate(gpu):
             assert np.array_equal(x, y)
     finally:
         gpu.set_tuning(128, 16, **before)
+
+
+def test_autotune_batch_tunes_the_merged_launch(gpu):
+    """A mixed batch whose buckets are each too small to fill the device runs
+    as one merged launch with the wildcard (0, 0) tuning: autotune_batch times
+    candidates for that entry, installs the fastest, and results stay equal."""
+    import torch
+    from helpers import make_plan, outputs
+    jobs = w.config_jobs("uneven_mix", count=600, cap=1 << 12)
+    plan, order = make_plan(gpu, jobs)
+    before = gpu.get_tuning(0, 0)
+
+    def decode():
+        p, _ = make_plan(gpu, jobs)
+        p.launch()
+        torch.cuda.synchronize()
+        return outputs(p)
+
+    ref = decode()
+    cands = [dict(before, low_bits=8), dict(before, low_bits=9), dict(before, grid_per_cu=6),
+             dict(before, node_cap=64)]
+    try:
+        res = gpu.autotune_batch(order, plan.code_index, plan.M, plan.cap, plan.noise_var,
+                                 plan.rx_offset, plan.rx, candidates=cands, reps=2)
+        timed = [t for t in res["table"] if t["ms"] is not None]
+        assert len(timed) >= 3
+        assert any(t["tuning"]["node_cap"] == 64 for t in [t for t in res["table"]
+                                                             if t["ms"] is None])
+        assert gpu.get_tuning(0, 0) == res["best"]
+        got = decode()
+        for x, y in zip(got[:4], ref[:4]):   # performed checks depend on the tuning
+            assert np.array_equal(x, y)
+    finally:
+        gpu.set_tuning(0, 0, **before)
