@@ -315,7 +315,7 @@ void grand_debug_fail_launches(uint32_t count);
  * `steps` x 8 dependent-free v_xor_b32 over 8 workgroups of 256 threads per
  * compute unit, synchronously on the null stream, and stores the achieved
  * lane-operations per second (and the timed launch's seconds, if `seconds`
- * is not null).  `steps` must be a positive multiple of 8.  Allocates and
+ * is not null).  `steps` must be a positive multiple of 8, at most 2^20.  Allocates and
  * frees a small device buffer.  Returns 0, GRAND_EINVAL for bad arguments,
  * GRAND_ENOMEM or GRAND_EDEVICE. */
 int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds);
@@ -330,7 +330,8 @@ int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds
  * pattern p flips bit j of p at position j * n / 16, j < 16.  One warm-up
  * launch, one timed launch, synchronously on the null stream; stores the
  * checks per second and (if not null) the number of zero syndromes found.
- * patterns <= 65536.  Allocates and frees a small device buffer.  Returns 0,
+ * patterns <= 65536 and words x patterns <= 2^32.  Allocates and frees a small
+ * device buffer.  Returns 0,
  * GRAND_EINVAL, GRAND_ENOMEM or GRAND_EDEVICE (also when the code lives on
  * another device). */
 int grand_probe_dense_pmult(const grand_code *code, uint32_t words, uint32_t patterns,

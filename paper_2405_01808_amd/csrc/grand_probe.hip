@@ -133,7 +133,8 @@ extern "C" int grand_probe_dense_pmult(const grand_code *code, uint32_t words,
                                        uint32_t patterns, double *checks_per_s,
                                        uint64_t *zero_syndromes)
 {
-    if (!code || !checks_per_s || words == 0 || patterns == 0 || patterns > 65536)
+    if (!code || !checks_per_s || words == 0 || patterns == 0 || patterns > 65536 ||
+        (uint64_t)words * patterns > (1ull << 32))
         return GRAND_EINVAL;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != code->device ||
@@ -184,7 +185,7 @@ done:
 
 extern "C" int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds)
 {
-    if (!lane_ops_per_s || steps == 0 || steps % kProbeUnroll)
+    if (!lane_ops_per_s || steps == 0 || steps % kProbeUnroll || steps > (1u << 20))
         return GRAND_EINVAL;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

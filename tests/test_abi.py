@@ -139,6 +139,7 @@ def test_xor_rate_probe_rejects_bad_arguments_on_host():
     assert L.grand_probe_xor_rate(0, ctypes.byref(r), None) == nat.GRAND_EINVAL
     assert L.grand_probe_xor_rate(12, ctypes.byref(r), None) == nat.GRAND_EINVAL   # not a multiple of 8
     assert L.grand_probe_xor_rate(8, None, None) == nat.GRAND_EINVAL
+    assert L.grand_probe_xor_rate((1 << 20) + 8, ctypes.byref(r), None) == nat.GRAND_EINVAL
 
 
 def test_dense_pmult_probe_rejects_bad_arguments_on_host():
