@@ -58,9 +58,10 @@ std::map<std::pair<uint32_t, uint32_t>, grand_tuning> g_tune;
 
 grand_tuning builtin_tuning(uint32_t n, uint32_t M)
 {
-    (void)M;
     grand_tuning t;
-    t.low_bits = (n && n <= 64) ? 8 : 9;
+    // short words of low order mostly decode early, where a smaller low
+    // table is cheaper to build; otherwise 2^9 entries (measured per bucket)
+    t.low_bits = (n && n <= 64 && M && M <= 16) ? 8 : 9;
     t.block = 256;
     t.first_band = 256;
     t.band_growth = 4;
