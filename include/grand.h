@@ -185,7 +185,10 @@ void grand_graph_destroy(grand_graph *graph);
 typedef struct {
     uint32_t low_bits;     /* b: the b cheapest flips form the sorted low table
                               (0..13, and 2^b <= 8 * block) */
-    uint32_t block;        /* threads per workgroup (64..256, multiple of 64) */
+    uint32_t block;        /* threads per workgroup (64..1024, multiple of 64).  A
+                              launch with at most (compute units / 4) words that
+                              keeps the default 256 runs 1024-thread workgroups
+                              instead, one word per compute unit */
     uint32_t first_band;   /* patterns aimed at by the first cost band (>= 1) */
     uint32_t band_growth;  /* each later band aims at growth x the patterns
                               checked so far (2..64) */

@@ -220,6 +220,19 @@ struct LaunchTarget {
     uint8_t *scratch;
 };
 
+// A launch of few words leaves most compute units idle: give each word a
+// 1024-thread workgroup (16 waves) instead of the default 256, when the
+// bucket's tuning still has the default block and even the wide launch
+// leaves the device under-filled.  Only the launch shape changes.
+void widen_small(DeviceCtx *ctx, std::vector<Bucket> &buckets)
+{
+    for (auto &bk : buckets)
+        if (bk.t.block == 256 && bk.words.size() * 4 <= (size_t)ctx->cus &&
+            4ull * lds_layout(bk.ni ? bk.ni : items_pow2(bk.n, bk.M), kMaxBlock,
+                              bk.t.low_bits).words + 256 <= kLdsPerWorkgroup)
+            bk.t.block = kMaxBlock;
+}
+
 // Workgroups per launch of each bucket and the store bytes they need.
 size_t bucket_grids(DeviceCtx *ctx, const std::vector<Bucket> &buckets, std::vector<uint32_t> &grids)
 {
@@ -348,6 +361,7 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
             std::stable_sort(bk.words.begin(), bk.words.end(), [&](uint32_t x, uint32_t y) {
                 return b->query_cap[x] > b->query_cap[y];
             });
+    widen_small(ctx, buckets);
     return GRAND_OK;
 }
 
@@ -587,6 +601,7 @@ int grand_decode_ex(const grand_code *code, const float *rx, uint32_t M, float n
     Bucket bk{code->n, M, tuning_for(code->n, M), {0}};
     bk.t.grid_per_cu = 1;
     std::vector<Bucket> buckets{bk};
+    widen_small(ctx, buckets);
     std::vector<uint32_t> base{0}, grids;
     rc = ensure_scratch(*r, bucket_grids(ctx, buckets, grids));
     if (rc)

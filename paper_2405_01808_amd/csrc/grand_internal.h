@@ -11,7 +11,7 @@ constexpr uint32_t kMaxN = 1024;        // block length
 constexpr uint32_t kMaxItems = 1024;    // 2L <= N for M >= 4
 constexpr uint32_t kMaxKW = 16;         // syndrome words (rows <= 512)
 constexpr uint32_t kMaxLowBits = 13;    // low table <= 8192 entries
-constexpr uint32_t kMaxBlock = 256;
+constexpr uint32_t kMaxBlock = 1024;   // launches of few words use 1024-thread workgroups
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kCwStride = 16;      // u64 words per codeword in batch outputs
 

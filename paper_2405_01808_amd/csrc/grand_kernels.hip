@@ -1078,11 +1078,9 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
     return w;
 }
 
-// At most 72 VGPRs (7 waves per SIMD): the kernel is bound by LDS and
-// memory latency, so more resident waves beat the few registers spilled.
-__global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
+// The persistent loop: each workgroup takes words until the batch is done.
+__device__ inline void decode_loop(const KernelArgs &a, Shared &sh)
 {
-    __shared__ Shared sh;
     extern __shared__ __align__(16) uint32_t dyn[];
     const Workspace w = workspace(a, dyn);
     for (;;) {
@@ -1104,6 +1102,23 @@ __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
     }
 }
 
+// Batches: 256 threads and at most 72 VGPRs (7 waves per SIMD); the kernel
+// is bound by LDS and memory latency, so more resident waves beat the few
+// registers spilled.
+__global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
+{
+    __shared__ Shared sh;
+    decode_loop(a, sh);
+}
+
+// Launches of few words: 1024 threads (16 waves) per word, so a word has a
+// whole compute unit's SIMDs; at most 128 VGPRs.
+__global__ __launch_bounds__(1024, 4) void grand_decode_kernel_wide(KernelArgs a)
+{
+    __shared__ Shared sh;
+    decode_loop(a, sh);
+}
+
 __global__ void zero_kernel(unsigned long long *p, uint32_t n)
 {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
@@ -1120,11 +1135,19 @@ int launch_zero(unsigned long long *p, uint32_t n, void *stream)
 
 int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stream)
 {
+    if (block > kMaxBlock || block % 64 || block == 0)
+        return -1;
     const uint32_t lds = 4u * lds_layout(a.ni, block, a.low_bits).words;
-    if (hipFuncSetAttribute((const void *)grand_decode_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    const void *fn = block > 256 ? (const void *)grand_decode_kernel_wide
+                                 : (const void *)grand_decode_kernel;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return -3;
-    hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    if (block > 256)
+        hipLaunchKernelGGL(grand_decode_kernel_wide, dim3(grid), dim3(block), lds,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), lds,
+                           (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -91,7 +91,9 @@ def test_tuning_table_roundtrip_and_validation():
     with pytest.raises(g.GrandError):              # 2^b above 8 merge outputs per thread
         g.set_tuning(2, 4096, block=64, low_bits=10)
     with pytest.raises(g.GrandError):
-        g.set_tuning(2, 4096, block=512)
+        g.set_tuning(2, 4096, block=1088)                 # above 1024 threads
+    g.set_tuning(2, 4096, block=512)                      # wide workgroups are valid
+    assert g.get_tuning(2, 4096)["block"] == 512
 
 
 def test_server_configuration_rejected_on_host():

@@ -86,9 +86,13 @@ def test_uneven_mix_batch(gpu):
                                     dict(low_bits=4, block=64, band_growth=64),
                                     dict(low_bits=11, block=256, node_cap=4096),
                                     dict(low_bits=6, first_band=1, node_cap=64),
-                                    dict(low_bits=10, block=128, first_band=100000)])
+                                    dict(low_bits=10, block=128, first_band=100000),
+                                    dict(block=512), dict(block=1024, low_bits=9),
+                                    dict(block=192, low_bits=7)])
 def test_results_do_not_depend_on_tuning(gpu, tuning):
-    """Every tuning must give the same exact answer."""
+    """Every tuning must give the same exact answer.  The batch is small, so
+    tunings that keep the default block of 256 run as 1024-thread workgroups;
+    block 512 and 1024 run the wide kernel as set, 64..192 the batch kernel."""
     jobs = w.jobs_from_spec("tune", seed=11, count=40, cap=4000, Ns=(64,), Ms=(16,),
                             ebn0=("uniform", 2.0, 9.0))
     saved = gpu.get_tuning(64, 16)
