@@ -186,9 +186,9 @@ typedef struct {
     uint32_t low_bits;     /* b: the b cheapest flips form the sorted low table
                               (0..13, and 2^b <= 8 * block) */
     uint32_t block;        /* threads per workgroup (64..1024, multiple of 64).  A
-                              launch with at most (compute units / 4) words that
+                              launch with at most one word per compute unit that
                               keeps the default 256 runs 1024-thread workgroups
-                              instead, one word per compute unit */
+                              instead */
     uint32_t first_band;   /* patterns aimed at by the first cost band (>= 1) */
     uint32_t band_growth;  /* each later band aims at growth x the patterns
                               checked so far (2..64) */

@@ -220,14 +220,18 @@ struct LaunchTarget {
     uint8_t *scratch;
 };
 
-// A launch of few words leaves most compute units idle: give each word a
-// 1024-thread workgroup (16 waves) instead of the default 256, when the
-// bucket's tuning still has the default block and even the wide launch
-// leaves the device under-filled.  Only the launch shape changes.
-void widen_small(DeviceCtx *ctx, std::vector<Bucket> &buckets)
+// A launch with no more words than compute units leaves most of each CU
+// idle: give each word a 1024-thread workgroup (16 waves) instead of the
+// default 256, when the bucket's tuning still has the default block.  Only
+// the launch shape changes.  (Measured at N = 128: faster up to one word per
+// CU, equal at 1.5, slower from 2.)  A symbol cut-off of at most 32
+// symbols leaves at most 64 flips per word, too little work for 16 waves.
+void widen_small(DeviceCtx *ctx, std::vector<Bucket> &buckets, uint32_t cutoff)
 {
+    if (cutoff != 0 && cutoff <= 32)
+        return;
     for (auto &bk : buckets)
-        if (bk.t.block == 256 && bk.words.size() * 4 <= (size_t)ctx->cus &&
+        if (bk.t.block == 256 && bk.words.size() <= (size_t)ctx->cus &&
             4ull * lds_layout(bk.ni ? bk.ni : items_pow2(bk.n, bk.M), kMaxBlock,
                               bk.t.low_bits).words + 256 <= kLdsPerWorkgroup)
             bk.t.block = kMaxBlock;
@@ -361,7 +365,7 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
             std::stable_sort(bk.words.begin(), bk.words.end(), [&](uint32_t x, uint32_t y) {
                 return b->query_cap[x] > b->query_cap[y];
             });
-    widen_small(ctx, buckets);
+    widen_small(ctx, buckets, b->cutoff_symbols);
     return GRAND_OK;
 }
 
@@ -601,7 +605,7 @@ int grand_decode_ex(const grand_code *code, const float *rx, uint32_t M, float n
     Bucket bk{code->n, M, tuning_for(code->n, M), {0}};
     bk.t.grid_per_cu = 1;
     std::vector<Bucket> buckets{bk};
-    widen_small(ctx, buckets);
+    widen_small(ctx, buckets, cutoff_symbols);
     std::vector<uint32_t> base{0}, grids;
     rc = ensure_scratch(*r, bucket_grids(ctx, buckets, grids));
     if (rc)

@@ -90,9 +90,10 @@ def test_uneven_mix_batch(gpu):
                                     dict(block=512), dict(block=1024, low_bits=9),
                                     dict(block=192, low_bits=7)])
 def test_results_do_not_depend_on_tuning(gpu, tuning):
-    """Every tuning must give the same exact answer.  The batch is small, so
-    tunings that keep the default block of 256 run as 1024-thread workgroups;
-    block 512 and 1024 run the wide kernel as set, 64..192 the batch kernel."""
+    """Every tuning must give the same exact answer.  The batch has fewer
+    words than compute units, so tunings that keep the default block of 256
+    run as 1024-thread workgroups; block 512 and 1024 run the wide kernel as
+    set, 64..192 the batch kernel."""
     jobs = w.jobs_from_spec("tune", seed=11, count=40, cap=4000, Ns=(64,), Ms=(16,),
                             ebn0=("uniform", 2.0, 9.0))
     saved = gpu.get_tuning(64, 16)
