@@ -62,12 +62,21 @@ grand_tuning builtin_tuning(uint32_t n, uint32_t M)
     // short words of low order mostly decode early, where a smaller low
     // table is cheaper to build; otherwise 2^9 entries (measured per bucket)
     t.low_bits = (n && n <= 64 && M && M <= 16) ? 8 : 9;
-    t.block = 256;
+    // long words carry more work per band: 512 threads (3 per CU, the wide
+    // kernel) beat 256 for n >= 256 in most (n, M) buckets measured
+    t.block = n >= 256 ? 512 : 256;
     t.first_band = 256;
     t.band_growth = 4;
     t.node_cap = 1u << 16;
-    t.grid_per_cu = 8;
+    t.grid_per_cu = n >= 256 ? 3 : 8;
     return t;
+}
+
+bool same_tuning(const grand_tuning &a, const grand_tuning &b)
+{
+    return a.low_bits == b.low_bits && a.block == b.block && a.first_band == b.first_band &&
+           a.band_growth == b.band_growth && a.node_cap == b.node_cap &&
+           a.grid_per_cu == b.grid_per_cu;
 }
 
 grand_tuning tuning_for(uint32_t n, uint32_t M)
@@ -221,9 +230,9 @@ struct LaunchTarget {
 };
 
 // A launch with no more words than compute units leaves most of each CU
-// idle: give each word a 1024-thread workgroup (16 waves) instead of the
-// default 256, when the bucket's tuning still has the default block.  Only
-// the launch shape changes.  (Measured at N = 128: faster up to one word per
+// idle: give each word a 1024-thread workgroup (16 waves), when the bucket
+// keeps the built-in tuning (or its block of 256).  Only the launch shape
+// changes.  (Measured at N = 128: faster up to one word per
 // CU, equal at 1.5, slower from 2.)  A symbol cut-off of at most 32
 // symbols leaves at most 64 flips per word, too little work for 16 waves.
 void widen_small(DeviceCtx *ctx, std::vector<Bucket> &buckets, uint32_t cutoff)
@@ -231,7 +240,8 @@ void widen_small(DeviceCtx *ctx, std::vector<Bucket> &buckets, uint32_t cutoff)
     if (cutoff != 0 && cutoff <= 32)
         return;
     for (auto &bk : buckets)
-        if (bk.t.block == 256 && bk.words.size() <= (size_t)ctx->cus &&
+        if ((bk.t.block == 256 || same_tuning(bk.t, builtin_tuning(bk.n, bk.M))) &&
+            bk.t.block < kMaxBlock && bk.words.size() <= (size_t)ctx->cus &&
             4ull * lds_layout(bk.ni ? bk.ni : items_pow2(bk.n, bk.M), kMaxBlock,
                               bk.t.low_bits).words + 256 <= kLdsPerWorkgroup)
             bk.t.block = kMaxBlock;
@@ -602,10 +612,9 @@ int grand_decode_ex(const grand_code *code, const float *rx, uint32_t M, float n
     HIP_TRY(hipMemcpyAsync(r->codes, r->h_codes, sizeof(DevCode), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(r->jobs, r->h_jobs, sizeof(DevJob), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(r->d_rx, r->h_rx, 2 * L * sizeof(float), hipMemcpyHostToDevice, st));
-    Bucket bk{code->n, M, tuning_for(code->n, M), {0}};
-    bk.t.grid_per_cu = 1;
-    std::vector<Bucket> buckets{bk};
+    std::vector<Bucket> buckets{Bucket{code->n, M, tuning_for(code->n, M), {0}}};
     widen_small(ctx, buckets, cutoff_symbols);
+    buckets[0].t.grid_per_cu = 1;
     std::vector<uint32_t> base{0}, grids;
     rc = ensure_scratch(*r, bucket_grids(ctx, buckets, grids));
     if (rc)
