@@ -18,12 +18,15 @@ from . import decoder
 
 
 def default_candidates(n: int, M: int) -> list[dict]:
+    """b in {8, 9, 10} x 6..8 workgroups of 256 threads per CU, and b = 9 x
+    2..4 workgroups of 512 threads per CU (long words gain from more waves
+    per word)."""
     base = decoder.get_tuning(n, M)
     out = []
     for low_bits, grid in itertools.product((8, 9, 10), (6, 7, 8)):
-        c = dict(base)
-        c.update(low_bits=low_bits, grid_per_cu=grid)
-        out.append(c)
+        out.append(dict(base, block=256, low_bits=low_bits, grid_per_cu=grid))
+    for grid in (2, 3, 4):
+        out.append(dict(base, block=512, low_bits=9, grid_per_cu=grid))
     return out
 
 
