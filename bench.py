@@ -275,8 +275,8 @@ def plain_small(g, w):
 
 def uneven_batch(g, w, reps: int = 5, tune: bool = True):
     """The uneven batch (16384 words, N in {64..512}, M in {4, 16, 64}, cap
-    2^18): autotune the merged launch's tuning on a 4096-word sample, then
-    time the whole batch eagerly and as a replayed HIP graph."""
+    2^18): autotune the merged launch's tuning on the batch, then time it
+    eagerly and as a replayed HIP graph."""
     import torch
     jobs = w.config_jobs("uneven_mix")
     codes, order = {}, []
@@ -297,10 +297,8 @@ def uneven_batch(g, w, reps: int = 5, tune: bool = True):
     tuned = None
     stream = torch.cuda.current_stream()
     try:
-        if tune:
-            k = 4096
-            tuned = g.autotune_batch(order, idx[:k], Ms[:k], caps[:k], nvs[:k], offs[:k], rx,
-                                     reps=2)
+        if tune:   # on the whole batch: the best launch shape depends on the word count
+            tuned = g.autotune_batch(order, idx, Ms, caps, nvs, offs, rx, reps=2)
         plan = g.BatchPlan(order, idx, Ms, caps, nvs, offs, rx)
         graph = g.BatchGraph(plan)
 

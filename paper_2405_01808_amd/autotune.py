@@ -1,6 +1,8 @@
 """Launch-shape autotuner for one (n, M) bucket.
 
-Times candidate tunings (grand_tuning_set) on a sample batch of that bucket,
+Times candidate tunings (grand_tuning_set) on a sample batch of that bucket
+(of the size the bucket's launches will have: the best workgroup size and
+count depend on how many words a launch holds),
 keeps only candidates whose outputs equal the first candidate's (a tuning
 changes the launch shape, never a result; a candidate whose node store
 overflows reports GRAND_ECAPACITY and is dropped), and installs the fastest.
