@@ -62,13 +62,11 @@ grand_tuning builtin_tuning(uint32_t n, uint32_t M)
     // short words of low order mostly decode early, where a smaller low
     // table is cheaper to build; otherwise 2^9 entries (measured per bucket)
     t.low_bits = (n && n <= 64 && M && M <= 16) ? 8 : 9;
-    // long words carry more work per band: 512 threads (3 per CU, the wide
-    // kernel) beat 256 for n >= 256 in most (n, M) buckets measured
-    t.block = n >= 256 ? 512 : 256;
+    t.block = 256;
     t.first_band = 256;
     t.band_growth = 4;
     t.node_cap = 1u << 16;
-    t.grid_per_cu = n >= 256 ? 3 : 8;
+    t.grid_per_cu = 8;
     return t;
 }
 
@@ -229,22 +227,39 @@ struct LaunchTarget {
     uint8_t *scratch;
 };
 
-// A launch with no more words than compute units leaves most of each CU
-// idle: give each word a 1024-thread workgroup (16 waves), when the bucket
-// keeps the built-in tuning (or its block of 256).  Only the launch shape
-// changes.  (Measured at N = 128: faster up to one word per
-// CU, equal at 1.5, slower from 2.)  A symbol cut-off of at most 32
-// symbols leaves at most 64 flips per word, too little work for 16 waves.
-void widen_small(DeviceCtx *ctx, std::vector<Bucket> &buckets, uint32_t cutoff)
+// Launch shapes for buckets that keep the built-in tuning (256 threads, 8
+// per CU, of which 7 are resident).  Only the shape changes, never a result.
+//   - No more words than compute units leaves most of each CU idle: one
+//     1024-thread workgroup (16 waves) per word.  (Measured at N = 128:
+//     faster up to one word per CU, equal at 1.5, slower from 2.)
+//   - Long words (n >= 256) filling at most two rounds of the resident
+//     narrow slots: 512-thread workgroups, 3 per CU.  A narrow launch there
+//     ends in a half-empty second round (cfg4's 2048 words: 1.71 instead of
+//     2.36 ms); beyond two rounds 256 threads win again (16384 words).
+// A symbol cut-off of at most 32 symbols leaves at most 64 flips per word,
+// too little work for wide workgroups.
+void shape_small(DeviceCtx *ctx, std::vector<Bucket> &buckets, uint32_t cutoff)
 {
     if (cutoff != 0 && cutoff <= 32)
         return;
-    for (auto &bk : buckets)
-        if ((bk.t.block == 256 || same_tuning(bk.t, builtin_tuning(bk.n, bk.M))) &&
-            bk.t.block < kMaxBlock && bk.words.size() <= (size_t)ctx->cus &&
-            4ull * lds_layout(bk.ni ? bk.ni : items_pow2(bk.n, bk.M), kMaxBlock,
-                              bk.t.low_bits).words + 256 <= kLdsPerWorkgroup)
+    const size_t cus = (size_t)ctx->cus;
+    for (auto &bk : buckets) {
+        if (!same_tuning(bk.t, builtin_tuning(bk.n, bk.M)) && bk.t.block != 256)
+            continue;
+        const uint32_t ni = bk.ni ? bk.ni : items_pow2(bk.n, bk.M);
+        auto fits = [&](uint32_t block) {
+            return 4ull * lds_layout(ni, block, bk.t.low_bits).words + 256 <= kLdsPerWorkgroup &&
+                   (1u << bk.t.low_bits) <= kMergePer * block;
+        };
+        const size_t words = bk.words.size();
+        if (words <= cus && fits(kMaxBlock)) {
             bk.t.block = kMaxBlock;
+        } else if (bk.n >= 256 && words <= 14 * cus && same_tuning(bk.t, builtin_tuning(bk.n, bk.M)) &&
+                   fits(512)) {
+            bk.t.block = 512;
+            bk.t.grid_per_cu = 3;
+        }
+    }
 }
 
 // Workgroups per launch of each bucket and the store bytes they need.
@@ -375,7 +390,7 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
             std::stable_sort(bk.words.begin(), bk.words.end(), [&](uint32_t x, uint32_t y) {
                 return b->query_cap[x] > b->query_cap[y];
             });
-    widen_small(ctx, buckets, b->cutoff_symbols);
+    shape_small(ctx, buckets, b->cutoff_symbols);
     return GRAND_OK;
 }
 
@@ -613,7 +628,7 @@ int grand_decode_ex(const grand_code *code, const float *rx, uint32_t M, float n
     HIP_TRY(hipMemcpyAsync(r->jobs, r->h_jobs, sizeof(DevJob), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(r->d_rx, r->h_rx, 2 * L * sizeof(float), hipMemcpyHostToDevice, st));
     std::vector<Bucket> buckets{Bucket{code->n, M, tuning_for(code->n, M), {0}}};
-    widen_small(ctx, buckets, cutoff_symbols);
+    shape_small(ctx, buckets, cutoff_symbols);
     buckets[0].t.grid_per_cu = 1;
     std::vector<uint32_t> base{0}, grids;
     rc = ensure_scratch(*r, bucket_grids(ctx, buckets, grids));
