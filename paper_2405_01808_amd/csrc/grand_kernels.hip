@@ -744,11 +744,25 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             dst = t;
         }
     }
-    for (uint32_t i = tid; i < LB; i += bs) {
-        uint32_t acc = 0;
-        for (uint32_t msk = lkey[i] & kMaskAll; msk; msk &= msk - 1)
-            acc ^= A.col0[__builtin_ctz(msk)];
-        ls0[i] = acc;
+    // leading syndrome words of the entries: the XOR of their flips'
+    // columns, read from two small tables (the XOR over every subset of the
+    // lower and of the upper half of the b flips), built in the staging area
+    // the merges no longer use
+    {
+        const uint32_t blo = (b + 1) / 2, nlo = 1u << blo, nhi = 1u << (b - blo);
+        for (uint32_t i = tid; i < nlo + nhi; i += bs) {
+            const bool upper = i >= nlo;
+            const uint32_t first = upper ? blo : 0u;
+            uint32_t acc = 0;
+            for (uint32_t z = upper ? i - nlo : i; z; z &= z - 1)
+                acc ^= A.col0[first + __builtin_ctz(z)];
+            ltmp[i] = acc;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < LB; i += bs) {
+            const uint32_t msk = lkey[i] & kMaskAll;
+            ls0[i] = ltmp[msk & (nlo - 1)] ^ ltmp[nlo + (msk >> blo)];
+        }
     }
     const uint32_t nbl = kBucketsPerKey * LB;
     const Buckets lbk{A.lidx, bucket_shift(lkey[LB - 1] >> kMaskBits, nbl), nbl};
