@@ -83,13 +83,12 @@ constexpr uint32_t kBucketsPerKey = 1;  // cost buckets per sorted key
 
 // Dynamic LDS of the decode kernel, in 32-bit words: the hard word and its
 // syndrome, the ranked flips and their columns' leading words (ni each),
-// the low flips' columns, scan partials, two sets of per-slot staging of a
-// block of nodes (one slot per thread, with run owners; the low table is
-// built in them before the bands start), bucket indexes of the ranked flips
-// and of the low table, and the low table (keys and leading syndrome words,
-// 2^b each).
+// the low flips' columns, per-slot staging of a block of nodes (one slot per
+// thread, with run owners; the low table is built in it before the bands
+// start), bucket indexes of the ranked flips and of the low table, and the
+// low table (keys and leading syndrome words, 2^b each).
 struct LdsLayout {
-    uint32_t yhat, s0, ikey, col0, lcol, wsum, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
+    uint32_t yhat, s0, ikey, col0, lcol, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
         ltmp, ls0, words;
 };
 
@@ -102,17 +101,21 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.ikey = o;  o += ni;
     L.col0 = o;  o += ni;
     L.lcol = o;  o += kMaxLowBits * kMaxKW;
-    L.wsum = o;  o += kMaxBlock / 64;
-    // two staging sets of one block each (set p at offset p * block); the
-    // low table's build buffer overlays them (12 * block >= 2^low_bits, as
-    // the host keeps 2^low_bits <= kMergePer * block)
+    // per-slot staging of a block of nodes (one slot per thread); the low
+    // table's build buffer (2^low_bits) and the cut-off's symbol scores (at
+    // most ni) overlay it, so it is at least that long
     L.ltmp = o;
-    L.foff = o;  o += 2 * block;
-    L.fa = o;    o += 2 * block;
-    L.fb = o;    o += 2 * block;
-    L.fcost = o; o += 2 * block;
-    L.flead = o; o += 2 * block;
-    L.fown = o;  o += 2 * block;
+    L.foff = o;  o += block;
+    L.fa = o;    o += block;
+    L.fb = o;    o += block;
+    L.fcost = o; o += block;
+    L.flead = o; o += block;
+    L.fown = o;  o += block;
+    {
+        const uint32_t need = (1u << low_bits) > ni ? (1u << low_bits) : ni;
+        if (o < L.ltmp + need)
+            o = L.ltmp + need;
+    }
     L.iidx = o;  o += kBucketsPerKey * ni + 2;
     L.lidx = o;  o += kBucketsPerKey * (1u << low_bits) + 2;
     o = (o + 1) & ~1u;          // 8-byte alignment of the table

@@ -74,13 +74,6 @@ struct Stage {
     uint32_t *fown;    // slot that owns the first entry of each thread's run
 };
 
-// Set `par` (0 or 1) of a staging area whose sets are `stride` words apart.
-__device__ inline Stage stage_set(const Stage &b, uint32_t par, uint32_t stride)
-{
-    const uint32_t o = par * stride;
-    return Stage{b.foff + o, b.fa + o, b.fb + o, b.fcost + o, b.flead + o, b.fown + o};
-}
-
 // Per-workgroup arrays in dynamic LDS, sized for the launch (lds_layout).
 struct Arr {
     uint32_t *yhat;    // hard word, 32-bit words
@@ -88,8 +81,7 @@ struct Arr {
     uint32_t *ikey;    // sorted flips (cost << 10 | position)
     uint32_t *col0;    // leading syndrome word of each rank's column
     uint32_t *lcol;    // full columns of the low flips
-    uint32_t *wsum;    // scan partials, one per wave
-    Stage st;          // staging: set p of a block starts at offset p * blockDim
+    Stage st;          // staging of a block, 64 slots per wave
     uint32_t *iidx;    // bucket index of the ranked flips
     uint32_t *lidx;    // bucket index of the low table
 };
@@ -130,25 +122,6 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Exclusive block-wide prefix sum of v; *total receives the sum.
-// Callers keep at least one barrier between two scans (wsum is reused).
-__device__ uint32_t block_exscan(uint32_t v, uint32_t *wsum, uint32_t *total)
-{
-    const uint32_t wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const uint32_t x = wave_incl_scan(v);
-    if (lane_id() == 63)
-        wsum[wid] = x;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-    for (uint32_t w = 0; w < nw; w++) {
-        const uint32_t sw = wsum[w];
-        base += w < wid ? sw : 0u;
-        tot += sw;
-    }
-    *total = tot;
-    return base + x - v;
 }
 
 // Bitonic sort of n (a power of two) keys in LDS, ascending.
@@ -1073,7 +1046,6 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
     w.A.ikey = dyn + ly.ikey;
     w.A.col0 = dyn + ly.col0;
     w.A.lcol = dyn + ly.lcol;
-    w.A.wsum = dyn + ly.wsum;
     w.A.st = Stage{dyn + ly.foff, dyn + ly.fa, dyn + ly.fb, dyn + ly.fcost, dyn + ly.flead,
                    dyn + ly.fown};
     w.A.iidx = dyn + ly.iidx;
