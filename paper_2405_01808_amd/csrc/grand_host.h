@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "grand.h"
 #include "grand_internal.h"
@@ -48,6 +49,11 @@ struct StreamRes {
     size_t h_codes_cap = 0;
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
+    // host copies of the tables that `jobs` and `codes` hold: a batch whose
+    // tables are identical launches on them without uploading again
+    std::vector<DevJob> up_jobs;
+    std::vector<DevCode> up_codes;
+    bool up_valid = false;
     // single-decode buffers
     float *d_rx = nullptr;
     uint64_t *d_out = nullptr;      // 16 cw words + q + checks
