@@ -102,8 +102,9 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.col0 = o;  o += ni;
     L.lcol = o;  o += kMaxLowBits * kMaxKW;
     // per-slot staging of a block of nodes (one slot per thread); the low
-    // table's build buffer (2^low_bits) and the cut-off's symbol scores (at
-    // most ni) overlay it, so it is at least that long
+    // table's build buffer (2^low_bits, then the subset tables of its two
+    // halves) and the cut-off's symbol scores (at most ni) overlay it, so it
+    // is at least that long
     L.ltmp = o;
     L.foff = o;  o += block;
     L.fa = o;    o += block;
@@ -112,7 +113,9 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.flead = o; o += block;
     L.fown = o;  o += block;
     {
-        const uint32_t need = (1u << low_bits) > ni ? (1u << low_bits) : ni;
+        const uint32_t lt = (1u << low_bits) + (1u << ((low_bits + 1) / 2)) +
+                            (1u << (low_bits / 2));
+        const uint32_t need = lt > ni ? lt : ni;
         if (o < L.ltmp + need)
             o = L.ltmp + need;
     }

@@ -192,12 +192,23 @@ __device__ inline uint32_t bucket_shift(uint32_t cmax, uint32_t nb)
     return s;
 }
 
+// The buckets up to the first key's and past the last key's are filled by
+// all threads together (they can be half the index); the ones between two
+// consecutive keys by the thread of the upper key.
 __device__ void build_buckets(const uint32_t *keys, uint32_t cnt, uint32_t kshift, uint32_t shift,
                               uint32_t nb, uint32_t *idx)
 {
-    for (uint32_t i = threadIdx.x; i <= cnt; i += blockDim.x) {
-        const uint32_t u0 = i == 0 ? 0u : ((keys[i - 1] >> kshift) >> shift) + 1;
-        const uint32_t u1 = i == cnt ? nb : min((keys[i] >> kshift) >> shift, nb);
+    const uint32_t head = cnt ? min((keys[0] >> kshift) >> shift, nb) : nb;
+    const uint32_t tail = cnt ? ((keys[cnt - 1] >> kshift) >> shift) + 1 : nb + 1;
+    for (uint32_t u = threadIdx.x; u <= nb; u += blockDim.x) {
+        if (u <= head)
+            idx[u] = 0;
+        else if (u >= tail)
+            idx[u] = cnt;
+    }
+    for (uint32_t i = 1 + threadIdx.x; i < cnt; i += blockDim.x) {
+        const uint32_t u0 = ((keys[i - 1] >> kshift) >> shift) + 1;
+        const uint32_t u1 = min((keys[i] >> kshift) >> shift, nb);
         for (uint32_t u = u0; u <= u1; u++)
             idx[u] = i;
     }
@@ -505,6 +516,93 @@ __device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t 
     }
 }
 
+// Low table: the 2^b subsets of the b cheapest flips as keys cost <<
+// kMaskBits | mask, ascending (cost, then colex, which is the mask's integer
+// order), with their leading syndrome words.  The subsets of the first b0 =
+// min(b, 6) flips are ranked in wave 0's registers: lane l holds subset l
+// and counts the smaller keys with readlane, with no LDS round trip.  Each
+// further flip j then merges the table with itself plus flip j (levels
+// alternate between two buffers, one barrier per level, starting in the
+// one that makes the last level land in lkey).  Node 0 (the empty high
+// subset) is stored while the merges run.
+__device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint32_t *ltmp,
+                                uint32_t *lkey, uint32_t *ls0)
+{
+    const uint32_t tid = threadIdx.x, bs = blockDim.x, LB = 1u << b;
+    const uint32_t b0 = min(b, 6u), n0 = 1u << b0;
+    uint32_t *src = ((b - b0) & 1) ? ltmp : lkey, *dst = ((b - b0) & 1) ? lkey : ltmp;
+    if (tid < 64) {
+        uint32_t key = 0xFFFFFFFFu;
+        if (tid < n0) {
+            uint32_t cost = 0;
+            for (uint32_t k = 0; k < b0; k++)
+                cost += (tid >> k) & 1u ? A.ikey[k] >> 10 : 0u;
+            key = (cost << kMaskBits) | tid;
+        }
+        uint32_t r = 0;
+        for (uint32_t m = 0; m < n0; m++)
+            r += (uint32_t)__builtin_amdgcn_readlane((int)key, (int)m) < key ? 1u : 0u;
+        if (tid < n0)
+            src[r] = key;
+    }
+    __syncthreads();   // also makes s(yhat) and the leading words visible
+    if (tid == 0) {
+        nd.cost[0] = 0;
+        nd.lead[0] = A.s0[0];
+        nd.par[0] = kNone;
+        nd.rl[0] = (uint16_t)b;
+        nd.ptr[0] = 0;
+        nd.cnext[0] = (uint16_t)b;
+    }
+    // XOR over every subset of the lower and of the upper half of the b
+    // flips' leading words, behind the merge buffer
+    const uint32_t blo = (b + 1) / 2, nlo = 1u << blo, nhi = 1u << (b - blo);
+    uint32_t *sub = ltmp + LB;
+    for (uint32_t i = tid; i < nlo + nhi; i += bs) {
+        const bool upper = i >= nlo;
+        const uint32_t first = upper ? blo : 0u;
+        uint32_t acc = 0;
+        for (uint32_t z = upper ? i - nlo : i; z; z &= z - 1)
+            acc ^= A.col0[first + __builtin_ctz(z)];
+        sub[i] = acc;
+    }
+    for (uint32_t j = b0; j < b; j++) {
+        const uint32_t len = 1u << j, outn = 2 * len;
+        const uint32_t add = ((A.ikey[j] >> 10) << kMaskBits) | (1u << j);
+        const uint32_t per = (outn + bs - 1) / bs;   // <= kMergePer (checked on the host)
+        const uint32_t i0 = min(outn, tid * per), i1 = min(outn, i0 + per);
+        if (i0 < i1) {
+            // co-rank: number of entries of the first list among the first
+            // i0 outputs
+            uint32_t lo = i0 > len ? i0 - len : 0, hi = min(i0, len);
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (src[mid] < src[i0 - mid - 1] + add)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            uint32_t ia = lo, ib = i0 - lo;
+            for (uint32_t o = i0; o < i1; o++) {
+                bool takeA = ib >= len || (ia < len && src[ia] < src[ib] + add);
+                dst[o] = takeA ? src[ia] : src[ib] + add;
+                ia += takeA;
+                ib += !takeA;
+            }
+        }
+        __syncthreads();
+        uint32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (b == b0)
+        __syncthreads();   // the subset tables
+    for (uint32_t i = tid; i < LB; i += bs) {
+        const uint32_t msk = lkey[i] & kMaskAll;
+        ls0[i] = sub[msk & (nlo - 1)] ^ sub[nlo + (msk >> blo)];
+    }
+}
+
 // Returns the word's output slot.
 __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
                                uint32_t *ltmp, uint32_t *ls0, const Nodes &nd, uint32_t jid)
@@ -680,75 +778,12 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         uint32_t r = i / kw, w = i % kw;
         A.lcol[i] = code.h_cols[(uint64_t)(A.ikey[r] & 1023u) * kw + w];
     }
-    // ---- low table: merge A = subsets of flips < j with A + flip j -------
-    // (levels alternate between two buffers, one barrier per level, starting
-    // in the one that makes the last level land in lkey)
-    {
-        uint32_t *src = (b & 1) ? ltmp : lkey, *dst = (b & 1) ? lkey : ltmp;
-        if (tid == 0)
-            src[0] = 0;
-        __syncthreads();
-        for (uint32_t j = 0; j < b; j++) {
-            const uint32_t len = 1u << j, outn = 2 * len;
-            const uint32_t add = ((A.ikey[j] >> 10) << kMaskBits) | (1u << j);
-            const uint32_t per = (outn + bs - 1) / bs;   // <= kMergePer (checked on the host)
-            const uint32_t i0 = min(outn, tid * per), i1 = min(outn, i0 + per);
-            if (i0 < i1) {
-                // co-rank: number of A entries among the first i0 outputs
-                uint32_t lo = i0 > len ? i0 - len : 0, hi = min(i0, len);
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (src[mid] < src[i0 - mid - 1] + add)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                uint32_t ia = lo, ib = i0 - lo;
-                for (uint32_t o = i0; o < i1; o++) {
-                    bool takeA = ib >= len || (ia < len && src[ia] < src[ib] + add);
-                    dst[o] = takeA ? src[ia] : src[ib] + add;
-                    ia += takeA;
-                    ib += !takeA;
-                }
-            }
-            __syncthreads();
-            uint32_t *t = src;
-            src = dst;
-            dst = t;
-        }
-    }
-    // leading syndrome words of the entries: the XOR of their flips'
-    // columns, read from two small tables (the XOR over every subset of the
-    // lower and of the upper half of the b flips), built in the staging area
-    // the merges no longer use
-    {
-        const uint32_t blo = (b + 1) / 2, nlo = 1u << blo, nhi = 1u << (b - blo);
-        for (uint32_t i = tid; i < nlo + nhi; i += bs) {
-            const bool upper = i >= nlo;
-            const uint32_t first = upper ? blo : 0u;
-            uint32_t acc = 0;
-            for (uint32_t z = upper ? i - nlo : i; z; z &= z - 1)
-                acc ^= A.col0[first + __builtin_ctz(z)];
-            ltmp[i] = acc;
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < LB; i += bs) {
-            const uint32_t msk = lkey[i] & kMaskAll;
-            ls0[i] = ltmp[msk & (nlo - 1)] ^ ltmp[nlo + (msk >> blo)];
-        }
-    }
+    // ---- low table: the 2^b subsets of the b cheapest flips in (cost,
+    // colex) order, with their leading syndrome words -------------------
+    build_low_table(A, nd, b, ltmp, lkey, ls0);
     const uint32_t nbl = kBucketsPerKey * LB;
     const Buckets lbk{A.lidx, bucket_shift(lkey[LB - 1] >> kMaskBits, nbl), nbl};
     build_buckets(lkey, LB, kMaskBits, lbk.shift, nbl, A.lidx);
-    // node 0: the empty high subset
-    if (tid == 0) {
-        nd.cost[0] = 0;
-        nd.lead[0] = A.s0[0];
-        nd.par[0] = kNone;
-        nd.rl[0] = (uint16_t)b;
-        nd.ptr[0] = 0;
-        nd.cnext[0] = (uint16_t)b;
-    }
     __syncthreads();
 
     // ---- bands ------------------------------------------------------------

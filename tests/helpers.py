@@ -102,3 +102,21 @@ def outputs(plan):
     o = plan.out
     return [t.cpu().numpy().copy() for t in (o.codewords, o.queries, o.abandoned, o.status,
                                               o.checks)]
+
+
+def gf2_rref(A):
+    """Reduced row echelon form over GF(2) (pivot columns left to right)."""
+    A = (np.array(A, dtype=np.uint8) & 1).copy()
+    r = 0
+    for c in range(A.shape[1]):
+        piv = [i for i in range(r, A.shape[0]) if A[i, c]]
+        if not piv:
+            continue
+        A[[r, piv[0]]] = A[[piv[0], r]]
+        for i in range(A.shape[0]):
+            if i != r and A[i, c]:
+                A[i] ^= A[r]
+        r += 1
+        if r == A.shape[0]:
+            break
+    return A

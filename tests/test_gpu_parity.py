@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workload as w
-from helpers import GpuCodes, assert_parity, gpu_batch, oracle_results
+from helpers import GpuCodes, assert_parity, gf2_rref, gpu_batch, oracle_results
 
 pytestmark = pytest.mark.gpu
 
@@ -164,3 +164,45 @@ def test_deterministic_across_runs(gpu):
     b = gpu_batch(jobs)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+class _BasisCodes(GpuCodes):
+    """Codes created from another basis of each H's row space."""
+
+    def __init__(self, basis):
+        super().__init__()
+        self.basis = basis
+
+    def index(self, N, K):
+        import paper_2405_01808_amd as g
+        if (N, K) not in self.codes:
+            self.codes[(N, K)] = (len(self.order), g.Code(N, self.basis(N, K)))
+            self.order.append(self.codes[(N, K)][1])
+        return self.codes[(N, K)][0]
+
+
+@pytest.mark.parametrize("N,M", [(128, 16), (256, 64)])
+def test_other_bases_of_h_decode_alike(gpu, N, M):
+    """The zero-syndrome test depends only on H's row space, so the RREF
+    basis (the one behind Section III's Table II) and a random row mix give
+    the oracle's frozen-column results, bit-exact."""
+    jobs = w.jobs_from_spec(f"basis{N}_{M}", seed=N + M, count=48, cap=5000, Ns=(N,), Ms=(M,),
+                            ebn0=("uniform", 2.0, 10.0))
+    orc = oracle_results(jobs)
+    rng = np.random.default_rng(N)
+
+    def rref(n, k):
+        return w.pack_bits(gf2_rref(w.polar_code(n, k).h_dense))
+
+    def mixed(n, k):
+        h = w.polar_code(n, k).h_dense
+        T = np.eye(h.shape[0], dtype=np.uint8)
+        for _ in range(4 * h.shape[0]):
+            i, j = rng.integers(0, h.shape[0], 2)
+            if i != j:
+                T[i] ^= T[j]
+        return w.pack_bits((T.astype(np.int64) @ h % 2).astype(np.uint8))
+
+    for name, basis in [("rref", rref), ("row mix", mixed)]:
+        say(f"basis {name} N={N} M={M}")
+        assert_parity(jobs, gpu_batch(jobs, _BasisCodes(basis)), orc, label=f"{name} {N}/{M}")
