@@ -876,6 +876,9 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             const uint32_t xs = wave_incl_scan(cnt);
             const uint32_t off = xs - cnt;
             const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
+            // slots with entries: a run steps from one to the next without
+            // reading the empty ones between
+            const unsigned long long nz = __ballot(cnt != 0);
             wave_sync();   // the previous block's runs are done with the staging
             S.fa[lane] = h;
             S.fb[lane] = lo;
@@ -891,13 +894,14 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             }
             wave_sync();
             wave_size += total;
-            const uint32_t ncnt = min(64u, used - c0);
             uint32_t j = lane * run;
             const uint32_t jend = min(total, j + run);
             if (j < jend) {
                 uint32_t k = S.fown[lane];
                 while (j < jend) {
-                    const uint32_t kend = k + 1 < ncnt ? S.foff[k + 1] : total;
+                    const unsigned long long later = k < 63 ? nz >> (k + 1) << (k + 1) : 0ull;
+                    const uint32_t kn = later ? (uint32_t)__builtin_ctzll(later) : 64u;
+                    const uint32_t kend = kn < 64 ? S.foff[kn] : total;
                     const uint32_t e = min(jend, kend);
                     const uint32_t l0 = S.fb[k] + (j - S.foff[k]);
                     const uint32_t cntk = e - j;
@@ -924,8 +928,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                                           l0 + t);
                     }
                     j = e;
-                    while (k + 1 < ncnt && S.foff[k + 1] <= j)
-                        k++;
+                    k = kn;   // the next piece, if any, is the next slot's
                 }
             }
         }
