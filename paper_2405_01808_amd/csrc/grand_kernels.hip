@@ -62,6 +62,7 @@ struct Shared {
     unsigned long long acc;
     unsigned long long wband[kMaxBlock / 64];   // each wave's checks in the band
     uint32_t alloc;                  // node slots claimed in the current expansion
+    uint32_t next;                   // next block of the check loop to take
 };
 
 // Per-slot staging of one block of nodes (one slot per thread).
@@ -784,6 +785,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     const uint32_t nbl = kBucketsPerKey * LB;
     const Buckets lbk{A.lidx, bucket_shift(lkey[LB - 1] >> kMaskBits, nbl), nbl};
     build_buckets(lkey, LB, kMaskBits, lbk.shift, nbl, A.lidx);
+    if (tid == 0)
+        sh.next = bs;
     __syncthreads();
 
     // ---- bands ------------------------------------------------------------
@@ -831,8 +834,9 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             break;
         const Thr kt = thr_of(vt, n);
 
-        // checks.  Each wave takes every nw-th block of 64 nodes on its own,
-        // with no workgroup barrier until the band ends: the block's ranges
+        // checks.  Each wave takes blocks of 64 nodes on its own (its first
+        // by its index, the others from a shared counter), with no workgroup
+        // barrier until the band ends: the block's ranges
         // are laid end to end (a wave scan) and cut into one run of
         // consecutive (node, entry) pairs per lane; each piece of a run that
         // belongs to one node is a tight comparison loop.
@@ -842,7 +846,6 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         // loop's bookkeeping in scalar registers)
         const uint32_t lane = lane_id(), nwv = bs >> 6;
         const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
-        const uint32_t wstride = nwv * 64;
         const Stage S = Stage{A.st.foff + wid * 64, A.st.fa + wid * 64, A.st.fb + wid * 64,
                               A.st.fcost + wid * 64, A.st.flead + wid * 64, A.st.fown + wid * 64};
         unsigned long long wave_size = 0;
@@ -856,22 +859,28 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             nx_lead = nd.lead[h];
             nx_rl = nd.rl[h];
         }
-        for (uint32_t c0 = wid * 64; c0 < used; c0 += wstride) {
+        for (uint32_t c0 = wid * 64; c0 < used;) {
             const uint32_t h = c0 + lane;
             uint32_t lo = nx_ptr, ch = nx_cost, lead = nx_lead, cnt = 0;
             const uint32_t rl = nx_rl;
-            if (h + wstride < used) {
-                nx_ptr = nd.ptr[h + wstride];
-                nx_cost = nd.cost[h + wstride];
-                nx_lead = nd.lead[h + wstride];
-                nx_rl = nd.rl[h + wstride];
-            }
+            // the wave's next block comes from a shared counter, so waves
+            // that finish early take more blocks
+            uint32_t cn = 0;
+            if (lane == 0)
+                cn = atomicAdd(&sh.next, 64u);
             if (h < used) {
                 uint32_t hi = node_end(lkey, lbk, LB, kt, (int32_t)ch, h, rl, lo);
                 if (hi > lo) {
                     cnt = hi - lo;
                     nd.ptr[h] = (uint16_t)hi;
                 }
+            }
+            cn = (uint32_t)__builtin_amdgcn_readlane((int)cn, 0);
+            if (cn + lane < used) {
+                nx_ptr = nd.ptr[cn + lane];
+                nx_cost = nd.cost[cn + lane];
+                nx_lead = nd.lead[cn + lane];
+                nx_rl = nd.rl[cn + lane];
             }
             const uint32_t xs = wave_incl_scan(cnt);
             const uint32_t off = xs - cnt;
@@ -931,6 +940,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                     k = kn;   // the next piece, if any, is the next slot's
                 }
             }
+            c0 = cn;
         }
         if (lane == 0)
             sh.wband[wid] = wave_size;
@@ -1029,6 +1039,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         vprev = vt;
         band++;
         target = min<uint64_t>(cap, cum * a.band_growth);
+        if (tid == 0)
+            sh.next = bs;
         __syncthreads();
     }
     __syncthreads();
