@@ -88,7 +88,8 @@ def test_uneven_mix_batch(gpu):
                                     dict(low_bits=6, first_band=1, node_cap=64),
                                     dict(low_bits=10, block=128, first_band=100000),
                                     dict(block=512), dict(block=1024, low_bits=9),
-                                    dict(block=192, low_bits=7)])
+                                    dict(block=192, low_bits=7),
+                                    dict(block=1024, low_bits=13)])
 def test_results_do_not_depend_on_tuning(gpu, tuning):
     """Every tuning must give the same exact answer.  The batch has fewer
     words than compute units, so tunings that keep the default block of 256
