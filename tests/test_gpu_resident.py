@@ -80,3 +80,17 @@ def test_new_received_values_behind_an_unchanged_table(gpu):
         rx.copy_(torch.from_numpy(np.concatenate([j.rx for j in jobs])))
         torch.cuda.synchronize()
         assert_parity(jobs, run(), oracle_results(jobs), label=name)
+
+
+def test_longer_batch_with_the_same_leading_words(gpu):
+    """A batch whose first words match the last upload but which has more
+    words uploads again; then the shorter batch again."""
+    codes = GpuCodes()
+    full = w.jobs_from_spec("prefix", seed=41, count=56, cap=3000, Ns=(64,), Ms=(16,),
+                            ebn0=("uniform", 2.0, 9.0))
+    short = full[:40]
+    orc_full, orc_short = oracle_results(full), oracle_results(short)
+    for name, jobs, orc in [("short", short, orc_short), ("full", full, orc_full),
+                            ("short again", short, orc_short)]:
+        say(name)
+        assert_parity(jobs, gpu_batch(jobs, codes), orc, label=name)
