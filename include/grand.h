@@ -152,7 +152,11 @@ typedef struct {
 /* Enqueue the decode of every codeword of the batch on `stream` (a
  * hipStream_t; NULL = the default stream) and return.  Outputs are valid
  * once the stream has completed.  Host-side validation errors are returned
- * directly and nothing is enqueued. */
+ * directly and nothing is enqueued.  The host arrays are read during the
+ * call only: the library builds the batch's job table from them and copies
+ * it to device memory it keeps per stream.  A call whose table is identical
+ * to the one last copied for the same stream (the same batch launched
+ * again) uses that copy instead of copying it again. */
 int grand_decode_batch(const grand_batch *batch, void *stream);
 
 /* ------------------------------------------------------------------ */
