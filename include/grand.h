@@ -139,7 +139,10 @@ typedef struct {
     uint64_t *queries_out;         /* device [count] */
     uint8_t *abandoned_out;        /* device [count] */
     int32_t *status_out;           /* device [count]: GRAND_OK, GRAND_EINVAL (bad rx values)
-                                      or GRAND_ECAPACITY; may be NULL */
+                                      or GRAND_ECAPACITY; may be NULL.  A word that fails
+                                      (any nonzero status) gets q = 0, abandoned = 1 and
+                                      an all-zero codeword, so the failure shows without
+                                      status_out (a decode never yields q = 0) */
     uint64_t *checks_out;          /* device [count]: syndrome checks actually performed
                                       (>= q; includes speculative checks); may be NULL */
     uint32_t cutoff_symbols;       /* Algorithm 2's cut-off S for every word: 0 searches the
@@ -147,9 +150,15 @@ typedef struct {
                                       S least reliable symbols (Steps 1-3), as in
                                       grand_decode_ex */
     uint32_t reserved;             /* must be 0 */
+    uint64_t rx_count;             /* floats in rx (> 0): every word's 2L values,
+                                      rx_offset[i] .. rx_offset[i] + 2L - 1, must lie
+                                      below it, or the call fails with GRAND_EINVAL */
 } grand_batch;
 
-/* Enqueue the decode of every codeword of the batch on `stream` (a
+/* Algorithm 2 (Section III) for every codeword of the batch, each word
+ * decoded exactly as grand_decode decodes it (grand_decode_ex with the
+ * batch's cutoff_symbols).
+ * Enqueue the decode of every codeword of the batch on `stream` (a
  * hipStream_t; NULL = the default stream) and return.  Outputs are valid
  * once the stream has completed.  Host-side validation errors are returned
  * directly and nothing is enqueued.  The host arrays are read during the
@@ -294,19 +303,23 @@ typedef struct {
 
 /* Replay an arrival stream in real time through the server: each request is
  * submitted at its arrival time (later if admission refuses), and the host
- * polls until every request has completed.  results[i] belongs to reqs[i];
- * its latency is complete_s - arrival_s.  *wall_s receives the replay's
- * duration. */
+ * polls until every request has completed.  rx (host) holds rx_count floats;
+ * request i reads 2L of them from reqs[i].rx_offset on, and a request whose
+ * code index, M or values fall outside is rejected with GRAND_EINVAL before
+ * the replay starts.  results[i] belongs to reqs[i]; its latency is
+ * complete_s - arrival_s.  *wall_s receives the replay's duration. */
 int grand_server_run_trace(grand_server *server, const grand_code *const *codes,
                            uint32_t n_codes, const grand_trace_req *reqs, uint32_t count,
-                           const float *rx, grand_result *results, double *wall_s);
+                           const float *rx, uint64_t rx_count, grand_result *results,
+                           double *wall_s);
 
 /* The same stream decoded one request per grand_decode call (one launch and
  * one synchronisation per request), in arrival order: the baseline the
- * server is compared with. */
+ * server is compared with.  Same arguments and validation as
+ * grand_server_run_trace. */
 int grand_plain_run_trace(const grand_code *const *codes, uint32_t n_codes,
                           const grand_trace_req *reqs, uint32_t count, const float *rx,
-                          grand_result *results, double *wall_s);
+                          uint64_t rx_count, grand_result *results, double *wall_s);
 
 /* Test hook for callers that exercise failure handling: the next `count`
  * server launches (process-wide) fail as if the launch call had failed.  Each

@@ -47,7 +47,8 @@ class GrandBatch(ctypes.Structure):
                 ("codeword_out", ctypes.c_void_p), ("queries_out", ctypes.c_void_p),
                 ("abandoned_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
                 ("checks_out", ctypes.c_void_p),
-                ("cutoff_symbols", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("cutoff_symbols", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("rx_count", ctypes.c_uint64)]
 
 
 class GrandServerConfig(ctypes.Structure):
@@ -145,11 +146,11 @@ def lib():
                                      ctypes.POINTER(u64)]
     L.grand_server_stats.restype = i32
     L.grand_server_run_trace.argtypes = [vp, ctypes.POINTER(vp), u32,
-                                         ctypes.POINTER(GrandTraceReq), u32, vp,
+                                         ctypes.POINTER(GrandTraceReq), u32, vp, u64,
                                          ctypes.POINTER(GrandResult), ctypes.POINTER(ctypes.c_double)]
     L.grand_server_run_trace.restype = i32
     L.grand_plain_run_trace.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(GrandTraceReq),
-                                        u32, vp, ctypes.POINTER(GrandResult),
+                                        u32, vp, u64, ctypes.POINTER(GrandResult),
                                         ctypes.POINTER(ctypes.c_double)]
     L.grand_plain_run_trace.restype = i32
     _lib = L

@@ -329,6 +329,8 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
         return fail(GRAND_EINVAL, "null pointer in batch");
     if (b->reserved != 0)
         return fail(GRAND_EINVAL, "reserved batch field must be 0");
+    if (b->rx_count == 0)
+        return fail(GRAND_EINVAL, "rx_count must give the number of floats in rx");
     if (b->n_codes == 0)
         return fail(GRAND_EINVAL, "no codes");
     for (uint32_t c = 0; c < b->n_codes; c++)
@@ -348,6 +350,11 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
             return fail(GRAND_EINVAL, "query cap out of range");
         if (!std::isfinite(b->noise_var[i]) || b->noise_var[i] <= 0.0f)
             return fail(GRAND_EINVAL, "noise variance must be finite and positive");
+        // the kernel reads 2L floats from rx_offset on: they must lie in rx
+        const uint64_t need = 2ull * symbols(b->codes[ci]->n, b->M[i]);
+        if (b->rx_offset[i] > b->rx_count || b->rx_count - b->rx_offset[i] < need)
+            return fail(GRAND_EINVAL, "word " + std::to_string(i) +
+                                          ": received values past rx_count");
         auto key = std::make_pair(b->codes[ci]->n, b->M[i]);
         if (last == SIZE_MAX || key != last_key) {
             auto it = index.find(key);

@@ -604,6 +604,21 @@ __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint3
     }
 }
 
+// Outputs of a word that could not be decoded (status < 0): q = 0 (never
+// the result of a decode), abandoned, an all-zero codeword.  Thread 0 only.
+__device__ void fail_word(const KernelArgs &a, uint32_t out_slot, int32_t status)
+{
+    uint64_t *cw = a.cw_out + (uint64_t)out_slot * kCwStride;
+    for (uint32_t w = 0; w < kCwStride; w++)
+        cw[w] = 0;
+    a.q_out[out_slot] = 0;
+    a.ab_out[out_slot] = 1;
+    if (a.status_out)
+        a.status_out[out_slot] = status;
+    if (a.checks_out)
+        a.checks_out[out_slot] = 0;
+}
+
 // Returns the word's output slot.
 __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
                                uint32_t *ltmp, uint32_t *ls0, const Nodes &nd, uint32_t jid)
@@ -618,8 +633,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     if (m == 0 || job.M != (1u << (2 * m)) || n_bits < 2 || n_bits > kMaxN || kw > kMaxKW ||
         2 * ((n_bits + 2 * m - 1) / (2 * m)) > a.ni) {
         // metadata the host never produces: fail the word rather than loop
-        if (threadIdx.x == 0 && a.status_out)
-            a.status_out[job.out] = -1;   // GRAND_EINVAL
+        if (threadIdx.x == 0)
+            fail_word(a, job.out, -1);   // GRAND_EINVAL
         return job.out;
     }
     const int32_t levels = 1 << m;
@@ -691,8 +706,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     __syncthreads();
     const uint32_t out_slot = job.out;
     if (sh.err) {
-        if (tid == 0 && a.status_out)
-            a.status_out[out_slot] = -1;   // GRAND_EINVAL
+        if (tid == 0)
+            fail_word(a, out_slot, -1);   // GRAND_EINVAL
         return out_slot;
     }
     // ---- Algorithm 2 Steps 1-3 (cut-off): only the flips of the S least
@@ -1047,7 +1062,9 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
 
     // ---- outputs ------------------------------------------------------
     const bool capacity_fail = !found && !abandon;
-    if (tid == 0) {
+    if (tid == 0 && capacity_fail) {
+        fail_word(a, out_slot, -5);   // GRAND_ECAPACITY
+    } else if (tid == 0) {
         uint32_t flips[kMaxN / 32];
         for (uint32_t w = 0; w < kMaxN / 32; w++)
             flips[w] = 0;
@@ -1074,7 +1091,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         a.q_out[out_slot] = q;
         a.ab_out[out_slot] = (uint8_t)(found ? 0 : 1);
         if (a.status_out)
-            a.status_out[out_slot] = capacity_fail ? -5 : 0;   // GRAND_ECAPACITY
+            a.status_out[out_slot] = 0;
         if (a.checks_out)
             a.checks_out[out_slot] = checks;
     }

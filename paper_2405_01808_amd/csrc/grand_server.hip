@@ -480,15 +480,32 @@ int grand_server_stats(grand_server *s, uint64_t *pending, uint64_t *running,
     return GRAND_OK;
 }
 
+// Every request of a trace names a code and reads 2L floats inside rx.
+static int check_trace(const grand_code *const *codes, uint32_t n_codes,
+                       const grand_trace_req *reqs, uint32_t count, uint64_t rx_count)
+{
+    for (uint32_t i = 0; i < count; i++) {
+        const grand_trace_req &r = reqs[i];
+        if (r.code_index >= n_codes || !codes[r.code_index])
+            return fail(GRAND_EINVAL, "trace request with a bad code index");
+        if (!valid_m(r.M))
+            return fail(GRAND_EINVAL, "trace request with an invalid M");
+        const uint64_t need = 2ull * symbols(codes[r.code_index]->n, r.M);
+        if (r.rx_offset > rx_count || rx_count - r.rx_offset < need)
+            return fail(GRAND_EINVAL, "trace request " + std::to_string(i) +
+                                          ": received values past rx_count");
+    }
+    return GRAND_OK;
+}
+
 int grand_server_run_trace(grand_server *s, const grand_code *const *codes, uint32_t n_codes,
                            const grand_trace_req *reqs, uint32_t count, const float *rx,
-                           grand_result *results, double *wall_s)
+                           uint64_t rx_count, grand_result *results, double *wall_s)
 {
     if (!s || !codes || !reqs || !rx || !results || n_codes == 0)
         return fail(GRAND_EINVAL, "null pointer");
-    for (uint32_t i = 0; i < count; i++)
-        if (reqs[i].code_index >= n_codes || !codes[reqs[i].code_index])
-            return fail(GRAND_EINVAL, "trace request with a bad code index");
+    if (int rc = check_trace(codes, n_codes, reqs, count, rx_count))
+        return rc;
     std::unordered_map<uint64_t, uint32_t> slot_of;
     std::vector<grand_result> buf(1024);
     const double t0 = now_s();
@@ -527,10 +544,12 @@ int grand_server_run_trace(grand_server *s, const grand_code *const *codes, uint
 
 int grand_plain_run_trace(const grand_code *const *codes, uint32_t n_codes,
                           const grand_trace_req *reqs, uint32_t count, const float *rx,
-                          grand_result *results, double *wall_s)
+                          uint64_t rx_count, grand_result *results, double *wall_s)
 {
     if (!codes || !reqs || !rx || !results || n_codes == 0)
         return fail(GRAND_EINVAL, "null pointer");
+    if (int rc = check_trace(codes, n_codes, reqs, count, rx_count))
+        return rc;
     const double t0 = now_s();
     for (uint32_t i = 0; i < count; i++) {
         const grand_trace_req &r = reqs[i];

@@ -17,6 +17,14 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
+def received_count(n: int, M: int) -> int:
+    """2L: the received floats of one word (L = ceil(n / log2 M) symbols)."""
+    m = int(M).bit_length() - 1
+    if M < 4 or M != 1 << m or m % 2:
+        raise ValueError(f"M must be 4, 16, 64, 256, 1024 or 4096, not {M}")
+    return 2 * (-(-int(n) // m))
+
+
 class Code:
     """Decoder handle for a parity-check matrix H (rows x n, bit-packed rows).
 
@@ -55,7 +63,10 @@ def decode(code: Code, rx, M: int, noise_var: float, cap: int, cutoff: int = 0):
     Algorithm 2's symbol cut-off S (grand_decode_ex).
 
     Returns (codeword uint64[ceil(n/64)], queries, abandoned)."""
-    r = np.ascontiguousarray(np.asarray(rx, dtype=np.float32))
+    r = np.ascontiguousarray(np.asarray(rx, dtype=np.float32)).reshape(-1)
+    if r.size < received_count(code.n, M):
+        raise ValueError(f"rx holds {r.size} values; a word of n={code.n}, M={M} needs "
+                         f"{received_count(code.n, M)}")
     cw = np.zeros((code.n + 63) // 64, np.uint64)
     q = ctypes.c_uint64(0)
     ab = ctypes.c_uint8(0)
@@ -63,6 +74,27 @@ def decode(code: Code, rx, M: int, noise_var: float, cap: int, cutoff: int = 0):
                                         int(cutoff), _ptr(cw), ctypes.byref(q),
                                         ctypes.byref(ab)))
     return cw, q.value, ab.value
+
+
+def check_batch_shapes(code_ns, code_index, M, cap, noise_var, rx_offset, rx_numel: int):
+    """Raise ValueError unless every per-word array has one entry per word,
+    every code index names a code, and every word's 2L received values lie
+    inside rx (rx_numel floats).  Host-side only: this is what keeps the
+    kernel's reads of rx in bounds."""
+    count = len(code_index)
+    for name, arr in (("M", M), ("cap", cap), ("noise_var", noise_var), ("rx_offset", rx_offset)):
+        if np.ndim(arr) != 1 or len(arr) != count:
+            raise ValueError(f"{name} has {np.size(arr)} entries; code_index has {count}")
+    if not count:
+        return
+    ci = np.asarray(code_index, np.int64)
+    if ci.min() < 0 or ci.max() >= len(code_ns):
+        raise ValueError("code_index out of range")
+    ns = np.asarray(code_ns, np.int64)[ci]
+    need = np.array([received_count(n, m) for n, m in zip(ns, np.asarray(M))], np.int64)
+    off = np.asarray(rx_offset, np.uint64)
+    if np.any(off > np.uint64(rx_numel)) or np.any(off.astype(np.int64) + need > rx_numel):
+        raise ValueError("a word's received values lie past the end of rx")
 
 
 @dataclass
@@ -90,6 +122,8 @@ class BatchPlan:
         if not (isinstance(rx, torch.Tensor) and rx.is_cuda and rx.dtype == torch.float32):
             raise TypeError("rx must be a float32 CUDA (HIP) tensor")
         self.rx = rx.contiguous()
+        check_batch_shapes([c.n for c in self.codes], self.code_index, self.M, self.cap,
+                           self.noise_var, self.rx_offset, self.rx.numel())
         dev = rx.device if device is None else device
         n = self.count
         self.out = BatchResult(
@@ -116,6 +150,7 @@ class BatchPlan:
         b.status_out = self.out.status.data_ptr()
         b.checks_out = self.out.checks.data_ptr()
         b.cutoff_symbols = int(cutoff)
+        b.rx_count = self.rx.numel()
         self.desc = b
 
     def launch(self, stream=None):

@@ -120,7 +120,7 @@ class Trace:
         wall = ctypes.c_double(0)
         nat.check(nat.lib().grand_server_run_trace(
             server.handle, ctypes.cast(self._handles, ctypes.POINTER(ctypes.c_void_p)),
-            len(self.codes), self.reqs, self.count, self.rx.ctypes.data, out,
+            len(self.codes), self.reqs, self.count, self.rx.ctypes.data, self.rx.size, out,
             ctypes.byref(wall)))
         return self._collect(out), wall.value
 
@@ -129,5 +129,5 @@ class Trace:
         wall = ctypes.c_double(0)
         nat.check(nat.lib().grand_plain_run_trace(
             ctypes.cast(self._handles, ctypes.POINTER(ctypes.c_void_p)), len(self.codes),
-            self.reqs, self.count, self.rx.ctypes.data, out, ctypes.byref(wall)))
+            self.reqs, self.count, self.rx.ctypes.data, self.rx.size, out, ctypes.byref(wall)))
         return self._collect(out), wall.value

@@ -47,6 +47,14 @@ int main()
     b.count = 0;
     EXPECT(grand_decode_batch(&b, nullptr) == GRAND_OK);   // empty batch: nothing to do
 
+    grand_trace_req tr;
+    std::memset(&tr, 0, sizeof(tr));
+    grand_result res;
+    double wall = 0;
+    const grand_code *const no_codes[1] = {nullptr};
+    EXPECT(grand_plain_run_trace(no_codes, 1, &tr, 1, rx, 64, &res, &wall) == GRAND_EINVAL);
+    EXPECT(grand_plain_run_trace(nullptr, 1, &tr, 1, rx, 64, &res, &wall) == GRAND_EINVAL);
+
     grand_tuning t;
     std::memset(&t, 0, sizeof(t));
     EXPECT(grand_tuning_get(128, 16, nullptr) == GRAND_EINVAL);

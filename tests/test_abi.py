@@ -149,3 +149,41 @@ def test_dense_pmult_probe_rejects_bad_arguments_on_host():
     L = nat.lib()
     r = ctypes.c_double()
     assert L.grand_probe_dense_pmult(None, 1, 1, ctypes.byref(r), None) == nat.GRAND_EINVAL
+
+
+def test_batch_shape_checks_on_host():
+    """Per-word arrays of the wrong length, a bad code index, and received
+    values past the end of rx are rejected before anything reaches the C ABI
+    (the kernel reads 2L floats from each word's offset)."""
+    from paper_2405_01808_amd.decoder import check_batch_shapes, received_count
+    assert received_count(128, 16) == 64
+    assert received_count(32, 64) == 12        # 6 symbols, pad bits in the last one
+    assert received_count(1024, 4) == 1024
+    with pytest.raises(ValueError):
+        received_count(128, 8)
+    ns = [128, 32]
+    ok = dict(code_index=[0, 1], M=[16, 64], cap=[10, 10], noise_var=[1.0, 1.0],
+              rx_offset=np.array([0, 64], np.uint64), rx_numel=76)
+    check_batch_shapes(ns, **ok)
+    with pytest.raises(ValueError):
+        check_batch_shapes(ns, **dict(ok, rx_numel=75))         # last word one float short
+    with pytest.raises(ValueError):
+        check_batch_shapes(ns, **dict(ok, rx_offset=np.array([0, 2**63], np.uint64)))
+    with pytest.raises(ValueError):
+        check_batch_shapes(ns, **dict(ok, M=[16]))              # short metadata
+    with pytest.raises(ValueError):
+        check_batch_shapes(ns, **dict(ok, noise_var=[1.0, 1.0, 1.0]))
+    with pytest.raises(ValueError):
+        check_batch_shapes(ns, **dict(ok, code_index=[0, 2]))
+    check_batch_shapes(ns, code_index=[], M=[], cap=[], noise_var=[],
+                       rx_offset=np.zeros(0, np.uint64), rx_numel=0)
+
+
+def test_single_decode_rejects_short_rx_on_host():
+    """decode() checks the length of rx before calling grand_decode_ex."""
+    import paper_2405_01808_amd as g
+
+    class FakeCode:
+        n, handle = 128, None
+    with pytest.raises(ValueError):
+        g.decode(FakeCode(), np.zeros(63, np.float32), 16, 1.0, 10)

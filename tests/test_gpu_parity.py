@@ -110,6 +110,8 @@ def test_results_do_not_depend_on_tuning(gpu, tuning):
         # GRAND_ECAPACITY, never a wrong answer
         ok = gst == 0
         assert np.all((gst == 0) | (gst == -5))
+        # a failed word shows without status_out: q = 0, abandoned, zero codeword
+        assert np.all(gq[~ok] == 0) and np.all(gab[~ok] == 1) and not gcw[~ok].any()
         idx = [i for i in range(len(jobs)) if ok[i]]
         assert_parity([jobs[i] for i in idx],
                       (gcw[idx], gq[idx], gab[idx], gst[idx], gchk[idx]),
@@ -157,6 +159,54 @@ def test_invalid_rx_reports_status(gpu):
     jobs[2].rx[5] = np.nan
     gcw, gq, gab, gst, gchk = gpu_batch(jobs)
     assert gst[2] == -1 and gst[0] == 0 and gst[1] == 0 and gst[3] == 0
+
+
+def test_invalid_rx_without_status_out(gpu):
+    """With status_out = NULL a word with a NaN value still shows its failure:
+    q = 0, abandoned = 1 and a zero codeword replace whatever the output
+    buffers held (here a previous launch's results)."""
+    import ctypes
+    import torch
+    from paper_2405_01808_amd import _native as nat
+    from helpers import make_plan
+    jobs = w.jobs_from_spec("bad", seed=2, count=6, cap=100, Ns=(32,), Ms=(4,),
+                            ebn0=("fixed", 3.0))
+    plan, _ = make_plan(gpu, jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    good_q = plan.out.queries.cpu().numpy().copy()
+    assert np.all(good_q >= 1)
+    plan.out.codewords.fill_(-1)
+    plan.rx[len(jobs[0].rx) * 3 + 1] = float("nan")    # word 3
+    plan.desc.status_out = None
+    plan.launch()
+    torch.cuda.synchronize()
+    q = plan.out.queries.cpu().numpy()
+    ab = plan.out.abandoned.cpu().numpy()
+    cw = plan.out.codewords.cpu().numpy()
+    assert q[3] == 0 and ab[3] == 1 and not cw[3].any()
+    keep = [i for i in range(len(jobs)) if i != 3]
+    assert np.array_equal(q[keep], good_q[keep])
+
+
+def test_batch_rejects_rx_past_rx_count(gpu):
+    """The C ABI itself rejects a word whose received values lie past
+    rx_count (the Python plan checks the same before calling it)."""
+    import ctypes
+    from paper_2405_01808_amd import _native as nat
+    from helpers import make_plan
+    jobs = w.jobs_from_spec("short", seed=3, count=4, cap=100, Ns=(64,), Ms=(16,),
+                            ebn0=("fixed", 6.0))
+    plan, _ = make_plan(gpu, jobs)
+    total = plan.desc.rx_count
+    plan.desc.rx_count = total - 1
+    rc = nat.lib().grand_decode_batch(ctypes.byref(plan.desc), None)
+    assert rc == nat.GRAND_EINVAL
+    assert b"rx_count" in nat.lib().grand_last_error()
+    plan.desc.rx_count = 0
+    assert nat.lib().grand_decode_batch(ctypes.byref(plan.desc), None) == nat.GRAND_EINVAL
+    plan.desc.rx_count = total
+    assert nat.lib().grand_decode_batch(ctypes.byref(plan.desc), None) == nat.GRAND_OK
 
 
 def test_deterministic_across_runs(gpu):
