@@ -76,3 +76,20 @@ def test_uneven_mix_full(gpu):
 
 def test_polar1024_256qam_full(gpu):
     run_config("polar1024_256qam", sample=16, seed=3)
+
+
+def test_polar1024_256qam_hits_match_oracle(gpu):
+    """The long-codeword config's words (N = 1024, 256-QAM, cap 2^20) at
+    Eb/N0 where the search finds codewords (15-19 dB; at the config's own
+    10-14 dB every word abandons): hits deep in the order and abandons, bit
+    exact with the oracle."""
+    jobs = w.jobs_from_spec("polar1024_256qam_hi", seed=40, count=32, cap=1 << 20, Ns=(1024,),
+                            Ms=(256,), ebn0=("uniform", 15.0, 19.0))
+    res = gpu_batch(jobs)
+    check_properties(jobs, res)
+    o = oracle_results(jobs)
+    ab = np.asarray(o[2])
+    q = np.asarray(o[1])
+    assert ab.sum() > 0 and (ab == 0).sum() > 0
+    assert np.any((ab == 0) & (q > 1000))
+    assert_parity(jobs, res, o, label="polar1024_256qam at 15-19 dB")

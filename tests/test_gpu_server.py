@@ -84,6 +84,28 @@ def test_mix_results_equal_single_decodes_and_oracle(gpu, persistent):
         assert np.array_equal(res[i].codeword[:nw], ocw[k]), i
 
 
+def test_serving_mix_at_full_cap_matches_oracle(gpu):
+    """The serving mix at its own query cap (2^18): 400 requests of the
+    Poisson stream served while others are in flight, every result equal to
+    the oracle's and to a single grand_decode of the same request."""
+    jobs = w.config_jobs("serving_mix", count=400, start=1000)
+    assert all(j.cap == 1 << 18 for j in jobs)
+    codes = Codes(gpu)
+    trace = make_trace(gpu, jobs, 2e5, codes)
+    srv = gpu.Server(max_inflight=1024, lanes=4, max_batch=64, memory_budget=4 << 30)
+    res, wall = trace.run_server(srv)
+    srv.close()
+    print(f"served {len(jobs)} requests at cap 2^18 in {wall * 1e3:.1f} ms", flush=True)
+    ocw, oq, oab = oracle_results(jobs)
+    assert 0 < int(np.sum(oab)) < len(jobs)          # both hits and abandons
+    for i, j in enumerate(jobs):
+        nw = (j.N + 63) // 64
+        assert res[i].status == 0, i
+        assert (res[i].queries, res[i].abandoned) == (int(oq[i]), int(oab[i])), (i, j.N, j.M)
+        assert np.array_equal(res[i].codeword[:nw], ocw[i]), i
+    assert_equal_single(gpu, codes, jobs[::8], res[::8])
+
+
 def test_admission_refusal_and_cancel_leave_no_state(gpu):
     codes = Codes(gpu)
     jobs = w.config_jobs("serving_mix", count=8, cap=1 << 10)
