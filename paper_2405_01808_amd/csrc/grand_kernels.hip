@@ -99,6 +99,14 @@ struct Nodes {
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
 
+// Threads per workgroup: a compile-time constant in the kernels built for
+// one launch shape (BS > 0), blockDim.x otherwise.
+template <uint32_t BS>
+__device__ inline uint32_t block_size()
+{
+    return BS ? BS : blockDim.x;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave, in data-parallel
 // primitives (DPP) instead of LDS round trips: shifts by 1, 2, 4 and 8
 // within each row of 16 lanes (lanes with no source add 0), then the last
@@ -126,11 +134,12 @@ __device__ inline void wave_sync()
 }
 
 // Bitonic sort of n (a power of two) keys in LDS, ascending.
+template <uint32_t BS>
 __device__ void bitonic_sort(uint32_t *a, uint32_t n)
 {
     for (uint32_t k = 2; k <= n; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            for (uint32_t i = threadIdx.x; i < n; i += block_size<BS>()) {
                 uint32_t ixj = i ^ j;
                 if (ixj > i) {
                     uint32_t x = a[i], y = a[ixj];
@@ -149,15 +158,16 @@ __device__ void bitonic_sort(uint32_t *a, uint32_t n)
 // Sort n <= 2 * blockDim distinct keys in LDS by counting, for each key,
 // the keys below it (one pass, all reads broadcast).  Pads (0xFFFFFFFF) are
 // first made distinct and stay above every real key.
+template <uint32_t BS>
 __device__ void rank_sort(uint32_t *a, uint32_t n)
 {
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+    for (uint32_t i = threadIdx.x; i < n; i += block_size<BS>())
         if (a[i] == 0xFFFFFFFFu)
             a[i] = 0xFFFF0000u | i;
     __syncthreads();
     uint32_t key[2] = {0, 0}, rank[2] = {0, 0};
     for (uint32_t c = 0; c < 2; c++) {
-        uint32_t i = threadIdx.x + c * blockDim.x;
+        uint32_t i = threadIdx.x + c * block_size<BS>();
         if (i < n) {
             key[c] = a[i];
             uint32_t r = 0;
@@ -168,7 +178,7 @@ __device__ void rank_sort(uint32_t *a, uint32_t n)
     }
     __syncthreads();
     for (uint32_t c = 0; c < 2; c++)
-        if (threadIdx.x + c * blockDim.x < n)
+        if (threadIdx.x + c * block_size<BS>() < n)
             a[rank[c]] = key[c];
     __syncthreads();
 }
@@ -196,18 +206,19 @@ __device__ inline uint32_t bucket_shift(uint32_t cmax, uint32_t nb)
 // The buckets up to the first key's and past the last key's are filled by
 // all threads together (they can be half the index); the ones between two
 // consecutive keys by the thread of the upper key.
+template <uint32_t BS>
 __device__ void build_buckets(const uint32_t *keys, uint32_t cnt, uint32_t kshift, uint32_t shift,
                               uint32_t nb, uint32_t *idx)
 {
     const uint32_t head = cnt ? min((keys[0] >> kshift) >> shift, nb) : nb;
     const uint32_t tail = cnt ? ((keys[cnt - 1] >> kshift) >> shift) + 1 : nb + 1;
-    for (uint32_t u = threadIdx.x; u <= nb; u += blockDim.x) {
+    for (uint32_t u = threadIdx.x; u <= nb; u += block_size<BS>()) {
         if (u <= head)
             idx[u] = 0;
         else if (u >= tail)
             idx[u] = cnt;
     }
-    for (uint32_t i = 1 + threadIdx.x; i < cnt; i += blockDim.x) {
+    for (uint32_t i = 1 + threadIdx.x; i < cnt; i += block_size<BS>()) {
         const uint32_t u0 = ((keys[i - 1] >> kshift) >> shift) + 1;
         const uint32_t u1 = min((keys[i] >> kshift) >> shift, nb);
         for (uint32_t u = u0; u <= u1; u++)
@@ -310,7 +321,16 @@ __device__ inline Thr thr_of(int64_t v, uint32_t n)
     return t;
 }
 
-__device__ inline int64_t thr_full(int64_t C, uint32_t n) { return C * (int64_t)(n + 1) + n; }
+// The band loop keeps thresholds as (C, R) pairs and divides only on the
+// rare store roll-back.
+__device__ inline int64_t thr_lin(Thr t, uint32_t n) { return (int64_t)t.C * (n + 1) + t.R; }
+__device__ inline bool thr_less(Thr a, Thr b) { return a.C < b.C || (a.C == b.C && a.R < b.R); }
+__device__ inline Thr thr_whole(int32_t C, uint32_t n) { return Thr{C, (int32_t)n}; }
+// the next threshold after t (admits one more rank step)
+__device__ inline Thr thr_succ(Thr t, uint32_t n)
+{
+    return t.R < (int32_t)n ? Thr{t.C, t.R + 1} : Thr{t.C + 1, 0};
+}
 
 // Exclusive end of the child ranks r in [rl, n) whose child (cost cp + c_r,
 // maxrank r) threshold k admits.  Costs ascend with r, so the admitted
@@ -376,31 +396,29 @@ __device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t lo, uint32_
     return lo;
 }
 
-// Raise the node store from "every high subset admitted by vE" to those
-// admitted by vwant.  The admitted child ranks of a parent form one
-// contiguous range; children of old parents not admitted by vE are new, and
+// Raise the node store from "every high subset admitted by kE" to those
+// admitted by kwant.  The admitted child ranks of a parent form one
+// contiguous range; children of old parents not admitted by kE are new, and
 // so are all admitted children of new parents, so the store grows one
 // forest level per pass.  Within a pass each wave takes every nw-th block of
 // 64 parents on its own and claims its children's slots with one LDS atomic
 // (slot order varies from run to run; nothing computed from the store
 // depends on it).  When the store would overflow, the step is rolled back
-// and the threshold gap halved.  Returns the threshold reached (vE when even
-// vE + 1 does not fit; sh.overflow is then set).
-__device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &nd,
-                                uint32_t n, uint32_t node_cap,
-                                int64_t vE, int64_t vwant)
+// and the threshold gap halved.  Returns the threshold reached (kE when even
+// the next threshold after kE does not fit; sh.overflow is then set).
+template <uint32_t BS>
+__device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &nd,
+                            uint32_t n, uint32_t node_cap, Thr kE, Thr kwant, uint32_t &used_out)
 {
-    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    const uint32_t tid = threadIdx.x, bs = block_size<BS>();
     const uint32_t lane = lane_id();
     const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
     const uint32_t wstride = bs;   // 64 parents per wave and block
     const Stage S = Stage{A.st.foff + wid * 64, A.st.fa + wid * 64, A.st.fb + wid * 64,
                           A.st.fcost + wid * 64, A.st.flead + wid * 64, A.st.fown + wid * 64};
     const uint32_t used0 = sh.used;
-    const Thr kE = thr_of(vE, n);
-    int64_t vn = vwant;
+    Thr kn = kwant;
     for (;;) {
-        const Thr kn = thr_of(vn, n);
         if (tid == 0)
             sh.alloc = used0;
         __syncthreads();
@@ -486,19 +504,22 @@ __device__ int64_t expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nod
             if (tid == 0)
                 sh.used = used;
             __syncthreads();
-            return vn;
+            used_out = used;
+            return kn;
         }
         // roll back: drop the new nodes and restore the old child frontiers
         for (uint32_t h = tid; h < used0; h += bs)
             nd.cnext[h] = (uint16_t)child_end(A.ikey, ibk, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
         __syncthreads();
+        const int64_t vE = thr_lin(kE, n), vn = thr_lin(kn, n);
         if (vn - vE <= 1) {
             if (tid == 0)
                 sh.overflow = 1;
             __syncthreads();
-            return vE;
+            used_out = used0;
+            return kE;
         }
-        vn = vE + (vn - vE) / 2;
+        kn = thr_of(vE + (vn - vE) / 2, n);
     }
 }
 
@@ -526,10 +547,11 @@ __device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t 
 // alternate between two buffers, one barrier per level, starting in the
 // one that makes the last level land in lkey).  Node 0 (the empty high
 // subset) is stored while the merges run.
+template <uint32_t BS>
 __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint32_t *ltmp,
                                 uint32_t *lkey, uint32_t *ls0)
 {
-    const uint32_t tid = threadIdx.x, bs = blockDim.x, LB = 1u << b;
+    const uint32_t tid = threadIdx.x, bs = block_size<BS>(), LB = 1u << b;
     const uint32_t b0 = min(b, 6u), n0 = 1u << b0;
     uint32_t *src = ((b - b0) & 1) ? ltmp : lkey, *dst = ((b - b0) & 1) ? lkey : ltmp;
     if (tid < 64) {
@@ -619,11 +641,13 @@ __device__ void fail_word(const KernelArgs &a, uint32_t out_slot, int32_t status
         a.checks_out[out_slot] = 0;
 }
 
-// Returns the word's output slot.
+// Returns the word's output slot.  LBITS > 0: the launch's low-table bits
+// are LBITS (a compile-time constant), else a.low_bits.
+template <uint32_t BS, uint32_t LBITS>
 __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, uint32_t *lkey,
                                uint32_t *ltmp, uint32_t *ls0, const Nodes &nd, uint32_t jid)
 {
-    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    const uint32_t tid = threadIdx.x, bs = block_size<BS>();
     const DevJob job = a.jobs[jid];
     const DevCode code = a.codes[job.code];
     const uint32_t n_bits = code.n, kw = code.kw;
@@ -754,12 +778,12 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     }
     // ---- Step 2: rank the flips --------------------------------------
     if (NI <= 256 && NI <= 2 * bs)
-        rank_sort(A.ikey, NI);
+        rank_sort<BS>(A.ikey, NI);
     else
-        bitonic_sort(A.ikey, NI);
+        bitonic_sort<BS>(A.ikey, NI);
     const uint32_t n = sh.nitems;
     const int32_t cmax = sh.cmax;
-    const uint32_t b = min(n, a.low_bits);
+    const uint32_t b = min(n, LBITS ? LBITS : a.low_bits);
     const uint32_t LB = 1u << b;
 
     // ---- Algorithm 1: s(yhat) = H yhat^T -----------------------------
@@ -786,7 +810,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     }
     const uint32_t nbi = kBucketsPerKey * NI;
     const Buckets ibk{A.iidx, bucket_shift(n ? A.ikey[n - 1] >> 10 : 0u, nbi), nbi};
-    build_buckets(A.ikey, n, 10, ibk.shift, nbi, A.iidx);
+    build_buckets<BS>(A.ikey, n, 10, ibk.shift, nbi, A.iidx);
     // leading words of every rank's column, full columns of the low flips
     for (uint32_t r = tid; r < n; r += bs)
         A.col0[r] = code.h_cols[(uint64_t)(A.ikey[r] & 1023u) * kw];
@@ -796,19 +820,20 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
     }
     // ---- low table: the 2^b subsets of the b cheapest flips in (cost,
     // colex) order, with their leading syndrome words -------------------
-    build_low_table(A, nd, b, ltmp, lkey, ls0);
+    build_low_table<BS>(A, nd, b, ltmp, lkey, ls0);
     const uint32_t nbl = kBucketsPerKey * LB;
     const Buckets lbk{A.lidx, bucket_shift(lkey[LB - 1] >> kMaskBits, nbl), nbl};
-    build_buckets(lkey, LB, kMaskBits, lbk.shift, nbl, A.lidx);
+    build_buckets<BS>(lkey, LB, kMaskBits, lbk.shift, nbl, A.lidx);
     if (tid == 0)
         sh.next = bs;
     __syncthreads();
 
     // ---- bands ------------------------------------------------------------
     const uint64_t cap = job.cap;
-    const int64_t vmax = thr_full(cmax, n);   // admits every pattern
-    int64_t vE = 0;                           // the store holds the empty high subset
-    int64_t vprev = -1;
+    const Thr kmax = thr_whole(cmax, n);       // admits every pattern
+    Thr kE{0, 0};                              // the store holds the empty high subset
+    Thr kprev{-1, (int32_t)n};                 // nothing checked yet
+    uint32_t used = 1;                         // nodes in the store (uniform)
     uint64_t cum = 0, checks = 0;
     float histC[2] = {0, 0}, histN[2] = {0, 0};
     uint32_t band = 0;
@@ -822,7 +847,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         // Only the amount of work per band depends on it, never the result:
         // the count grows roughly like a power of the cost threshold, so
         // the next threshold extrapolates the last two bands on a log scale.
-        const float cp = (float)thr_of(max<int64_t>(vprev, 0), n).C;
+        const float cp = (float)max(kprev.C, 0);
         float cd;
         if (band == 0) {
             uint64_t k = min<uint64_t>(target, max(1u, LB / 4)) - 1;
@@ -838,16 +863,18 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         }
         if (!(cd < 4.0e7f))
             cd = 4.0e7f;
-        int64_t vt = thr_full((int64_t)cd, n);
-        vt = min(vt, vmax);
-        vt = max(vt, vprev + 1);
-        if (vt > vE) {
-            vt = expand_nodes(sh, A, ibk, nd, n, a.node_cap, vE, vt);
-            vE = max(vE, vt);
+        Thr kt = thr_whole((int32_t)cd, n);
+        if (thr_less(kmax, kt))
+            kt = kmax;
+        if (thr_less(kt, thr_succ(kprev, n)))
+            kt = thr_succ(kprev, n);
+        if (thr_less(kE, kt)) {
+            kt = expand_nodes<BS>(sh, A, ibk, nd, n, a.node_cap, kE, kt, used);
+            if (thr_less(kE, kt))
+                kE = kt;
         }
-        if (vt <= vprev)      // the store cannot grow any further
+        if (!thr_less(kprev, kt))      // the store cannot grow any further
             break;
-        const Thr kt = thr_of(vt, n);
 
         // checks.  Each wave takes blocks of 64 nodes on its own (its first
         // by its index, the others from a shared counter), with no workgroup
@@ -856,7 +883,6 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         // consecutive (node, entry) pairs per lane; each piece of a run that
         // belongs to one node is a tight comparison loop.
         LaneHit best{0xFFFFFFFFu, kNone, 0};
-        const uint32_t used = sh.used;
         // (the wave index is uniform in a wave: readfirstlane keeps the
         // loop's bookkeeping in scalar registers)
         const uint32_t lane = lane_id(), nwv = bs >> 6;
@@ -1042,7 +1068,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             abandon = true;
             break;
         }
-        if (vt >= vmax) {          // every pattern has been checked
+        if (!thr_less(kt, kmax)) {     // every pattern has been checked
             q = cum;
             abandon = true;
             break;
@@ -1051,7 +1077,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         histN[0] = histN[1];
         histC[1] = (float)kt.C + (float)kt.R / (float)(n + 1);
         histN[1] = (float)cum;
-        vprev = vt;
+        kprev = kt;
         band++;
         target = min<uint64_t>(cap, cum * a.band_growth);
         if (tid == 0)
@@ -1104,9 +1130,12 @@ struct Workspace {
     Nodes nd;
 };
 
+// With BS, NI and LB given (> 0) every LDS offset is a compile-time constant.
+template <uint32_t BS, uint32_t NI, uint32_t LB>
 __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
 {
-    const LdsLayout ly = lds_layout(a.ni, blockDim.x, a.low_bits);
+    const LdsLayout ly = (BS && NI && LB) ? lds_layout(NI, BS, LB)
+                                          : lds_layout(a.ni, blockDim.x, a.low_bits);
     Workspace w;
     w.A.yhat = dyn + ly.yhat;
     w.A.s0 = dyn + ly.s0;
@@ -1132,10 +1161,11 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
 }
 
 // The persistent loop: each workgroup takes words until the batch is done.
+template <uint32_t BS, uint32_t NI, uint32_t LB>
 __device__ inline void decode_loop(const KernelArgs &a, Shared &sh)
 {
     extern __shared__ __align__(16) uint32_t dyn[];
-    const Workspace w = workspace(a, dyn);
+    const Workspace w = workspace<BS, NI, LB>(a, dyn);
     for (;;) {
         if (threadIdx.x == 0) {
             const unsigned long long c = atomicAdd(a.queue, 1ull) - a.qbase;
@@ -1146,7 +1176,7 @@ __device__ inline void decode_loop(const KernelArgs &a, Shared &sh)
         __syncthreads();
         if (jid == kNone)
             break;
-        const uint32_t out = decode_one(a, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, jid);
+        const uint32_t out = decode_one<BS, LB>(a, sh, w.A, w.lkey, w.ltmp, w.ls0, w.nd, jid);
         // thread 0 wrote every output of the word: publish them, then the flag
         if (a.done_out && threadIdx.x == 0)
             __hip_atomic_store(&a.done_out[out], a.done_seq, __ATOMIC_RELEASE,
@@ -1161,7 +1191,17 @@ __device__ inline void decode_loop(const KernelArgs &a, Shared &sh)
 __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
 {
     __shared__ Shared sh;
-    decode_loop(a, sh);
+    decode_loop<0, 0, 0>(a, sh);
+}
+
+// The same for one launch shape fixed at compile time (256 threads, next
+// power of two of 2L = NI, low table of 2^LB): LDS offsets and loop strides
+// become immediates, which frees scalar registers.
+template <uint32_t NI, uint32_t LB>
+__global__ __launch_bounds__(256, 7) void grand_decode_kernel_fixed(KernelArgs a)
+{
+    __shared__ Shared sh;
+    decode_loop<256, NI, LB>(a, sh);
 }
 
 // Launches of few words: 1024 threads (16 waves) per word, so a word has a
@@ -1169,7 +1209,7 @@ __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
 __global__ __launch_bounds__(1024, 4) void grand_decode_kernel_wide(KernelArgs a)
 {
     __shared__ Shared sh;
-    decode_loop(a, sh);
+    decode_loop<0, 0, 0>(a, sh);
 }
 
 __global__ void zero_kernel(unsigned long long *p, uint32_t n)
@@ -1191,16 +1231,19 @@ int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stre
     if (block > kMaxBlock || block % 64 || block == 0)
         return -1;
     const uint32_t lds = 4u * lds_layout(a.ni, block, a.low_bits).words;
-    const void *fn = block > 256 ? (const void *)grand_decode_kernel_wide
-                                 : (const void *)grand_decode_kernel;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -3;
+    void (*fn)(KernelArgs) = grand_decode_kernel;
     if (block > 256)
-        hipLaunchKernelGGL(grand_decode_kernel_wide, dim3(grid), dim3(block), lds,
-                           (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL(grand_decode_kernel, dim3(grid), dim3(block), lds,
-                           (hipStream_t)stream, a);
+        fn = grand_decode_kernel_wide;
+    else if (block == 256 && a.low_bits == 9 && a.ni == 64)     // N = 128, 16-QAM
+        fn = grand_decode_kernel_fixed<64, 9>;
+    else if (block == 256 && a.low_bits == 9 && a.ni == 512)    // merged batches up to N = 512
+        fn = grand_decode_kernel_fixed<512, 9>;
+    else if (block == 256 && a.low_bits == 9 && a.ni == 1024)   // merged batches up to N = 1024
+        fn = grand_decode_kernel_fixed<1024, 9>;
+    if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+        return -3;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
