@@ -169,6 +169,40 @@ typedef struct {
 int grand_decode_batch(const grand_batch *batch, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Many decodes without any allocation                                 */
+/* ------------------------------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batch
+ * decode of grand_decode_batch, with the same arguments, validation, errors
+ * and outputs (bit-identical results), that allocates nothing.  Its work
+ * counter, per-word tables and high-subset node stores live in one static
+ * device array of GRAND_NOALLOC_SCRATCH_BYTES that every device the library
+ * runs on holds until the process ends.
+ *   - at most GRAND_NOALLOC_MAX_WORDS codewords and GRAND_NOALLOC_MAX_CODES
+ *     codes per call (larger batches: GRAND_EINVAL, nothing enqueued);
+ *   - the words run as one launch in the caller's order, with node stores of
+ *     16384 nodes per workgroup (the default store holds 65536): a word that
+ *     cannot reach its answer or cap within them reports GRAND_ECAPACITY in
+ *     status_out (q = 0, abandoned = 1).  (Measured largest stores: 10690
+ *     nodes over the 8192 words of the N = 128 16-QAM batch, 27171 over
+ *     8192 words of the uneven N = 64..512 mix, up to 65256 for N = 1024
+ *     256-QAM at cap 2^20.);
+ *   - the per-word host arrays are copied to the device before the call
+ *     returns, so the call waits for work already queued on `stream` (it
+ *     cannot be recorded into a HIP graph);
+ *   - every call on a device shares that device's array, and the last call
+ *     leaves its contents there: calls whose launches overlap on one device
+ *     (on different streams or threads) race and give wrong results.  Issue
+ *     them on one stream, or order them.
+ * grand_init takes the array's device address; otherwise the first call on
+ * a device does. */
+#define GRAND_NOALLOC_SCRATCH_BYTES (512ull << 20)
+#define GRAND_NOALLOC_MAX_WORDS 65536u
+#define GRAND_NOALLOC_MAX_CODES 64u
+int grand_decode_batch_noalloc(const grand_batch *batch, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Batch graphs (for callers that decode batches of one fixed shape    */
 /* over and over, e.g. a receiver's frames: one call per batch)        */
 /* ------------------------------------------------------------------ */

@@ -29,7 +29,10 @@ EXPORTS = [
     "grand_server_cancel", "grand_server_poll", "grand_server_stats", "grand_server_run_trace",
     "grand_plain_run_trace", "grand_graph_create", "grand_graph_launch", "grand_graph_destroy",
     "grand_debug_fail_launches", "grand_probe_xor_rate", "grand_probe_dense_pmult",
+    "grand_decode_batch_noalloc",
 ]
+NOALLOC_MAX_WORDS = 65536
+NOALLOC_MAX_CODES = 64
 
 
 class GrandTuning(ctypes.Structure):
@@ -111,6 +114,8 @@ def lib():
     L.grand_decode_ex.restype = i32
     L.grand_decode_batch.argtypes = [ctypes.POINTER(GrandBatch), vp]
     L.grand_decode_batch.restype = i32
+    L.grand_decode_batch_noalloc.argtypes = [ctypes.POINTER(GrandBatch), vp]
+    L.grand_decode_batch_noalloc.restype = i32
     L.grand_graph_create.argtypes = [ctypes.POINTER(GrandBatch), ctypes.POINTER(vp)]
     L.grand_graph_create.restype = i32
     L.grand_graph_launch.argtypes = [vp, vp]

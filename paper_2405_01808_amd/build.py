@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgrand.so")
-SOURCES = ["grand_kernels.hip", "grand_api.hip", "grand_server.hip", "grand_probe.hip"]
+SOURCES = ["grand_kernels.hip", "grand_api.hip", "grand_server.hip", "grand_probe.hip",
+           "grand_noalloc.hip"]
 ARCH = os.environ.get("GRAND_OFFLOAD_ARCH", "gfx950")
 
 

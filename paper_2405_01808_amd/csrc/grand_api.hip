@@ -516,7 +516,10 @@ int grand_init(int device)
         return fail(GRAND_EINVAL, "no such device");
     HIP_TRY(hipSetDevice(device));
     DeviceCtx *ctx;
-    return current_ctx(&ctx);
+    int rc = current_ctx(&ctx);
+    if (rc)
+        return rc;
+    return noalloc_setup(device, nullptr);
 }
 
 int grand_code_create(uint32_t n, uint32_t rows, const uint64_t *h_rows, grand_code **out)

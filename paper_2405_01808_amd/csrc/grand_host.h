@@ -86,5 +86,9 @@ int ensure_scratch(StreamRes &r, size_t bytes);
 int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream,
                     int mixed);
 
+// Device address of the no-alloc entry point's static array on `device`
+// (taken with hipGetSymbolAddress the first time; *out may be null).
+int noalloc_setup(int device, uint8_t **out);
+
 }  // namespace host
 }  // namespace grand

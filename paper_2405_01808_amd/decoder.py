@@ -162,6 +162,17 @@ class BatchPlan:
         nat.check(nat.lib().grand_decode_batch(ctypes.byref(self.desc), ctypes.c_void_p(sp)))
         return self.out
 
+    def launch_noalloc(self, stream=None):
+        """The same decode through grand_decode_batch_noalloc (no device
+        allocation; returns once the per-word tables are on the device)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.rx.device)
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        nat.check(nat.lib().grand_decode_batch_noalloc(ctypes.byref(self.desc),
+                                                       ctypes.c_void_p(sp)))
+        return self.out
+
 
 class BatchGraph:
     """A BatchPlan recorded once as a HIP graph (grand_graph_*): each launch

@@ -46,6 +46,11 @@ int main()
     EXPECT(grand_decode_batch(&b, nullptr) == GRAND_EINVAL);
     b.count = 0;
     EXPECT(grand_decode_batch(&b, nullptr) == GRAND_OK);   // empty batch: nothing to do
+    EXPECT(grand_decode_batch_noalloc(nullptr, nullptr) == GRAND_EINVAL);
+    EXPECT(grand_decode_batch_noalloc(&b, nullptr) == GRAND_OK);
+    b.count = 1;
+    EXPECT(grand_decode_batch_noalloc(&b, nullptr) == GRAND_EINVAL);   // null arrays
+    b.count = 0;
 
     grand_trace_req tr;
     std::memset(&tr, 0, sizeof(tr));

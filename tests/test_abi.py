@@ -187,3 +187,15 @@ def test_single_decode_rejects_short_rx_on_host():
         n, handle = 128, None
     with pytest.raises(ValueError):
         g.decode(FakeCode(), np.zeros(63, np.float32), 16, 1.0, 10)
+
+
+def test_noalloc_entry_rejects_bad_batches_on_host():
+    """grand_decode_batch_noalloc rejects a null batch and null arrays, and
+    accepts an empty batch, before touching a device."""
+    from paper_2405_01808_amd import _native as nat
+    L = nat.lib()
+    assert L.grand_decode_batch_noalloc(None, None) == nat.GRAND_EINVAL
+    b = nat.GrandBatch()
+    assert L.grand_decode_batch_noalloc(ctypes.byref(b), None) == nat.GRAND_OK
+    b.count = 1
+    assert L.grand_decode_batch_noalloc(ctypes.byref(b), None) == nat.GRAND_EINVAL
