@@ -149,11 +149,17 @@ typedef struct {
                                       full pattern space; S > 0 keeps only the flips of the
                                       S least reliable symbols (Steps 1-3), as in
                                       grand_decode_ex */
-    uint32_t reserved;             /* must be 0 */
+    uint32_t launch_mode;          /* GRAND_LAUNCH_AUTO: one launch per (n, M) bucket when some
+                                      bucket fills the device alone, else one merged launch;
+                                      GRAND_LAUNCH_MERGED: one launch for every word;
+                                      GRAND_LAUNCH_BUCKETS: one launch per (n, M) bucket, each
+                                      with that bucket's tuning.  Results do not depend on it */
     uint64_t rx_count;             /* floats in rx (> 0): every word's 2L values,
                                       rx_offset[i] .. rx_offset[i] + 2L - 1, must lie
                                       below it, or the call fails with GRAND_EINVAL */
 } grand_batch;
+
+enum { GRAND_LAUNCH_AUTO = 0, GRAND_LAUNCH_MERGED = 1, GRAND_LAUNCH_BUCKETS = 2 };
 
 /* Algorithm 2 (Section III) for every codeword of the batch, each word
  * decoded exactly as grand_decode decodes it (grand_decode_ex with the
@@ -181,7 +187,8 @@ int grand_decode_batch(const grand_batch *batch, void *stream);
  * runs on holds until the process ends.
  *   - at most GRAND_NOALLOC_MAX_WORDS codewords and GRAND_NOALLOC_MAX_CODES
  *     codes per call (larger batches: GRAND_EINVAL, nothing enqueued);
- *   - the words run as one launch in the caller's order, with node stores of
+ *   - the words run as one launch in the caller's order (whatever
+ *     launch_mode asks), with node stores of
  *     16384 nodes per workgroup (the default store holds 65536): a word that
  *     cannot reach its answer or cap within them reports GRAND_ECAPACITY in
  *     status_out (q = 0, abandoned = 1).  (Measured largest stores: 10690
@@ -255,7 +262,8 @@ int grand_tuning_set(uint32_t n, uint32_t M, const grand_tuning *t);
 /* Serving: continuously batched decoding of a request stream          */
 /* ------------------------------------------------------------------ */
 
-/* A server admits requests (Algorithm 2 decodes, one codeword each) as they
+/* A server admits requests (Algorithm 2 decodes, one codeword each, each as
+ * grand_decode decodes it) as they
  * arrive, within a slot count and a device-memory budget, and keeps several
  * HIP streams ("lanes") busy.  Whenever a lane is free, every admitted
  * request not yet on the device (up to max_batch) is written into the lane's
@@ -280,7 +288,15 @@ typedef struct {
     uint32_t mode;             /* GRAND_SERVE_LANES or GRAND_SERVE_PERSISTENT */
     uint64_t memory_budget;    /* device bytes reserved for admitted requests;
                                   each reserves grand_request_bytes(n, M) */
+    uint32_t wide_lanes;       /* 0, or the number of the lanes (< lanes) that serve only
+                                  long words, 2L >= GRAND_WIDE_ITEMS received values
+                                  (e.g. N = 512 and 1024 with QPSK, N = 1024 with 16-QAM):
+                                  each such request gets one 1024-thread workgroup, a
+                                  whole compute unit, and the other lanes take the rest */
+    uint32_t pad;              /* must be 0 */
 } grand_server_config;
+
+#define GRAND_WIDE_ITEMS 512u
 
 typedef struct {
     uint64_t request_id;
@@ -374,22 +390,39 @@ void grand_debug_fail_launches(uint32_t count);
  * GRAND_ENOMEM or GRAND_EDEVICE. */
 int grand_probe_xor_rate(uint32_t steps, double *lane_ops_per_s, double *seconds);
 
+/* Algorithm 1 (pMult, Section III) and its Theorem on a batch of vectors:
+ * syndromes[i] = H x_i^T over GF(2) for the code's H, one full product per
+ * vector (the packed rows in LDS; per row the AND with the vector, the XOR
+ * fold of the products and their parity, which is the Theorem's addition
+ * tree over the row's support).
+ *   x          device, count x ceil(n/64) uint64 (bit order as h_rows; bits
+ *              past n must be zero);
+ *   syndromes  device, count x ceil(rows/64) uint64: bit r of vector i's
+ *              syndrome is bit r % 64 of syndromes[i * ceil(rows/64) + r/64];
+ *   stream     hipStream_t (NULL = the default stream); asynchronous.
+ * Returns GRAND_OK, GRAND_EINVAL (null pointer with count > 0) or
+ * GRAND_EDEVICE (also when the code lives on another device). */
+int grand_pmult(const grand_code *code, const uint64_t *x, uint32_t count, uint64_t *syndromes,
+                void *stream);
+
 /* Baseline for the incremental syndrome: the paper's Step 5 model, one full
  * Algorithm 1 product s = H (yhat + e)^T per test error pattern (bit-packed
  * rows of `code` in LDS; per row an AND with the word, an XOR fold and a
- * parity).  Runs `words` x `patterns` checks: word w is a hash-generated hard
- * word (bit i of 32-bit word k is bit i of hash(w, k), with
- * hash(a, b) = f(a * 0x9E3779B1 ^ (b + 0x7F4A7C15) * 0x85EBCA77) and
- * f(h) = ((h ^ h >> 15) * 0x2C1B3C6D) ^ (... >> 12), bits past n cleared);
- * pattern p flips bit j of p at position j * n / 16, j < 16.  One warm-up
- * launch, one timed launch, synchronously on the null stream; stores the
- * checks per second and (if not null) the number of zero syndromes found.
- * patterns <= 65536 and words x patterns <= 2^32.  Allocates and frees a small
- * device buffer.  Returns 0,
- * GRAND_EINVAL, GRAND_ENOMEM or GRAND_EDEVICE (also when the code lives on
- * another device). */
-int grand_probe_dense_pmult(const grand_code *code, uint32_t words, uint32_t patterns,
-                            double *checks_per_s, uint64_t *zero_syndromes);
+ * parity), with no pattern generation, ordering or early exit.  Runs
+ * `words` x `patterns` checks: word w is words_dev[w] (device, ceil(n/64)
+ * uint64 each: e.g. the hard decisions of received words), or, when
+ * words_dev is NULL, a hash-generated word (bit i of 32-bit word k is bit i
+ * of hash(w, k), with hash(a, b) = f(a * 0x9E3779B1 ^ (b + 0x7F4A7C15) *
+ * 0x85EBCA77) and f(h) = ((h ^ h >> 15) * 0x2C1B3C6D) ^ (... >> 12), bits
+ * past n cleared); pattern p flips bit j of p at position j * n / 16,
+ * j < 16.  One warm-up launch, one timed launch, synchronously on the null
+ * stream; stores the checks per second and (if not null) the number of zero
+ * syndromes found.  patterns <= 65536 and words x patterns <= 2^32.
+ * Allocates and frees a small device buffer.  Returns 0, GRAND_EINVAL,
+ * GRAND_ENOMEM or GRAND_EDEVICE (also when the code lives on another
+ * device). */
+int grand_probe_dense_pmult(const grand_code *code, const uint64_t *words_dev, uint32_t words,
+                            uint32_t patterns, double *checks_per_s, uint64_t *zero_syndromes);
 
 #ifdef __cplusplus
 }

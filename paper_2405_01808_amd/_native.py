@@ -19,6 +19,7 @@ GRAND_MAX_CAP = 1 << 40
 CW_STRIDE = 16   # uint64 words per codeword in batch outputs
 SERVE_LANES = 0
 SERVE_PERSISTENT = 1
+LAUNCH_AUTO, LAUNCH_MERGED, LAUNCH_BUCKETS = 0, 1, 2
 
 # Every symbol the header declares; tests check that the library exports them.
 EXPORTS = [
@@ -29,7 +30,7 @@ EXPORTS = [
     "grand_server_cancel", "grand_server_poll", "grand_server_stats", "grand_server_run_trace",
     "grand_plain_run_trace", "grand_graph_create", "grand_graph_launch", "grand_graph_destroy",
     "grand_debug_fail_launches", "grand_probe_xor_rate", "grand_probe_dense_pmult",
-    "grand_decode_batch_noalloc",
+    "grand_decode_batch_noalloc", "grand_pmult",
 ]
 NOALLOC_MAX_WORDS = 65536
 NOALLOC_MAX_CODES = 64
@@ -50,14 +51,18 @@ class GrandBatch(ctypes.Structure):
                 ("codeword_out", ctypes.c_void_p), ("queries_out", ctypes.c_void_p),
                 ("abandoned_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
                 ("checks_out", ctypes.c_void_p),
-                ("cutoff_symbols", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("cutoff_symbols", ctypes.c_uint32), ("launch_mode", ctypes.c_uint32),
                 ("rx_count", ctypes.c_uint64)]
 
 
 class GrandServerConfig(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("mode", ctypes.c_uint32),
-                ("memory_budget", ctypes.c_uint64)]
+                ("memory_budget", ctypes.c_uint64), ("wide_lanes", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+WIDE_ITEMS = 512   # GRAND_WIDE_ITEMS: 2L from which a request goes to the wide lanes
 
 
 class GrandResult(ctypes.Structure):
@@ -127,8 +132,10 @@ def lib():
     L.grand_probe_xor_rate.argtypes = [u32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]
     L.grand_probe_xor_rate.restype = i32
-    L.grand_probe_dense_pmult.argtypes = [vp, u32, u32, ctypes.POINTER(ctypes.c_double),
+    L.grand_probe_dense_pmult.argtypes = [vp, vp, u32, u32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_uint64)]
+    L.grand_pmult.argtypes = [vp, vp, u32, vp, vp]
+    L.grand_pmult.restype = i32
     L.grand_probe_dense_pmult.restype = i32
     L.grand_tuning_get.argtypes = [u32, u32, ctypes.POINTER(GrandTuning)]
     L.grand_tuning_get.restype = i32

@@ -320,15 +320,15 @@ int enqueue_buckets(const LaunchTarget &lt, const std::vector<Bucket> &buckets,
 
 // Validate a batch and group its words into launches ("buckets"), each in
 // the order its workgroups should take them.
-int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Bucket> &buckets)
+int plan_batch(DeviceCtx *ctx, const grand_batch *b, std::vector<Bucket> &buckets)
 {
     if (!b)
         return fail(GRAND_EINVAL, "null batch");
     if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
         !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
         return fail(GRAND_EINVAL, "null pointer in batch");
-    if (b->reserved != 0)
-        return fail(GRAND_EINVAL, "reserved batch field must be 0");
+    if (b->launch_mode > GRAND_LAUNCH_BUCKETS)
+        return fail(GRAND_EINVAL, "launch_mode must be GRAND_LAUNCH_AUTO, _MERGED or _BUCKETS");
     if (b->rx_count == 0)
         return fail(GRAND_EINVAL, "rx_count must give the number of floats in rx");
     if (b->n_codes == 0)
@@ -369,6 +369,8 @@ int plan_batch(DeviceCtx *ctx, const grand_batch *b, int mixed, std::vector<Buck
         buckets[last].words.push_back(i);
     }
     bool merged = false;
+    int mixed = b->launch_mode == GRAND_LAUNCH_MERGED ? 1
+                : b->launch_mode == GRAND_LAUNCH_BUCKETS ? 0 : -1;
     // One launch for the whole batch when asked, or when no (n, M) bucket
     // fills the device on its own: words of every size share the persistent
     // workgroups (LDS sized for the largest), heaviest first.
@@ -430,12 +432,12 @@ void fill_tables(const grand_batch *b, const std::vector<Bucket> &buckets, DevJo
 
 // Validate a batch, bucket it by (n, M), stage its jobs and enqueue the
 // launches on `stream` using the buffers of `r`.
-int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream, int mixed)
+int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream)
 {
     if (b && b->count == 0)
         return GRAND_OK;
     std::vector<Bucket> buckets;
-    int rc = plan_batch(ctx, b, mixed, buckets);
+    int rc = plan_batch(ctx, b, buckets);
     if (rc)
         return rc;
     rc = init_stream_res(r);
@@ -725,7 +727,7 @@ int grand_graph_create(const grand_batch *b, grand_graph **out)
     if (rc)
         return rc;
     std::vector<Bucket> buckets;
-    rc = plan_batch(ctx, b, -1, buckets);
+    rc = plan_batch(ctx, b, buckets);
     if (rc)
         return rc;
     std::vector<DevJob> jobs(b->count);
@@ -803,7 +805,7 @@ int grand_decode_batch(const grand_batch *b, void *stream)
     rc = stream_res(ctx, stream, &r);
     if (rc)
         return rc;
-    return decode_batch_on(ctx, *r, b, stream, -1);
+    return decode_batch_on(ctx, *r, b, stream);
 }
 
 }  // extern "C"

@@ -81,10 +81,9 @@ int init_stream_res(StreamRes &r);
 // Grow r's high-subset stores to `bytes` (synchronises the device when an
 // existing buffer has to be replaced).
 int ensure_scratch(StreamRes &r, size_t bytes);
-// mixed: 1 = one launch for all words, 0 = one launch per (n, M) bucket,
-// -1 = one launch when no bucket fills the device on its own.
-int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream,
-                    int mixed);
+// Plan (b->launch_mode decides merged or per-bucket launches), stage and
+// enqueue a batch on `stream` with the buffers of r.
+int decode_batch_on(DeviceCtx *ctx, StreamRes &r, const grand_batch *b, void *stream);
 
 // Device address of the no-alloc entry point's static array on `device`
 // (taken with hipGetSymbolAddress the first time; *out may be null).

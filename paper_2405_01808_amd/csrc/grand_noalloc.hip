@@ -101,8 +101,8 @@ extern "C" int grand_decode_batch_noalloc(const grand_batch *b, void *stream)
     if (!b->codes || !b->code_index || !b->M || !b->query_cap || !b->noise_var ||
         !b->rx_offset || !b->rx || !b->codeword_out || !b->queries_out || !b->abandoned_out)
         return fail(GRAND_EINVAL, "null pointer in batch");
-    if (b->reserved != 0)
-        return fail(GRAND_EINVAL, "reserved batch field must be 0");
+    if (b->launch_mode > GRAND_LAUNCH_BUCKETS)
+        return fail(GRAND_EINVAL, "launch_mode must be GRAND_LAUNCH_AUTO, _MERGED or _BUCKETS");
     if (b->rx_count == 0)
         return fail(GRAND_EINVAL, "rx_count must give the number of floats in rx");
     if (b->count > GRAND_NOALLOC_MAX_WORDS)

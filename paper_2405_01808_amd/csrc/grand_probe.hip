@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "grand.h"
 #include "grand_host.h"
 
@@ -59,6 +61,7 @@ __device__ inline uint32_t probe_hash(uint32_t a, uint32_t b)
 template <uint32_t N>
 __global__ __launch_bounds__(256) void dense_pmult_kernel(const uint32_t *h_rows, uint32_t rows,
                                                           uint64_t checks, uint32_t patterns,
+                                                          const uint32_t *words,
                                                           unsigned long long *zeros)
 {
     constexpr uint32_t W = N <= 64 ? 2u : N / 32u;   // 32-bit words per packed row
@@ -75,7 +78,8 @@ __global__ __launch_bounds__(256) void dense_pmult_kernel(const uint32_t *h_rows
         for (uint32_t k = 0; k < W; k++) {
             const uint32_t valid = N >= 32 * (k + 1) ? 0xFFFFFFFFu
                                    : (N <= 32 * k ? 0u : (1u << (N - 32 * k)) - 1u);
-            x[k] = probe_hash(wi, k) & valid;
+            // the caller's hard words (W 32-bit words each), or hashed ones
+            x[k] = (words ? words[(uint64_t)wi * W + k] : probe_hash(wi, k)) & valid;
         }
 #pragma unroll
         for (uint32_t j = 0; j < 16; j++) {
@@ -98,39 +102,91 @@ __global__ __launch_bounds__(256) void dense_pmult_kernel(const uint32_t *h_rows
 
 template <uint32_t N>
 int launch_dense(const grand_code *c, uint32_t grid, uint64_t checks, uint32_t patterns,
-                 unsigned long long *zeros)
+                 const uint32_t *words, unsigned long long *zeros)
 {
     const uint32_t lds = c->rows * c->row_w32 * 4u;
     if (hipFuncSetAttribute((const void *)dense_pmult_kernel<N>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return GRAND_EDEVICE;
     hipLaunchKernelGGL(dense_pmult_kernel<N>, dim3(grid), dim3(256), lds, 0, c->d_rows, c->rows,
-                       checks, patterns, zeros);
+                       checks, patterns, words, zeros);
     return hipGetLastError() == hipSuccess ? 0 : GRAND_EDEVICE;
 }
 
 int launch_dense_any(const grand_code *c, uint32_t grid, uint64_t checks, uint32_t patterns,
-                     unsigned long long *zeros)
+                     const uint32_t *words, unsigned long long *zeros)
 {
     switch (c->n) {
-    case 2: return launch_dense<2>(c, grid, checks, patterns, zeros);
-    case 4: return launch_dense<4>(c, grid, checks, patterns, zeros);
-    case 8: return launch_dense<8>(c, grid, checks, patterns, zeros);
-    case 16: return launch_dense<16>(c, grid, checks, patterns, zeros);
-    case 32: return launch_dense<32>(c, grid, checks, patterns, zeros);
-    case 64: return launch_dense<64>(c, grid, checks, patterns, zeros);
-    case 128: return launch_dense<128>(c, grid, checks, patterns, zeros);
-    case 256: return launch_dense<256>(c, grid, checks, patterns, zeros);
-    case 512: return launch_dense<512>(c, grid, checks, patterns, zeros);
-    case 1024: return launch_dense<1024>(c, grid, checks, patterns, zeros);
+    case 2: return launch_dense<2>(c, grid, checks, patterns, words, zeros);
+    case 4: return launch_dense<4>(c, grid, checks, patterns, words, zeros);
+    case 8: return launch_dense<8>(c, grid, checks, patterns, words, zeros);
+    case 16: return launch_dense<16>(c, grid, checks, patterns, words, zeros);
+    case 32: return launch_dense<32>(c, grid, checks, patterns, words, zeros);
+    case 64: return launch_dense<64>(c, grid, checks, patterns, words, zeros);
+    case 128: return launch_dense<128>(c, grid, checks, patterns, words, zeros);
+    case 256: return launch_dense<256>(c, grid, checks, patterns, words, zeros);
+    case 512: return launch_dense<512>(c, grid, checks, patterns, words, zeros);
+    case 1024: return launch_dense<1024>(c, grid, checks, patterns, words, zeros);
     default: return GRAND_EINVAL;
+    }
+}
+
+// Algorithm 1 for a batch of vectors: thread i forms s = H x_i^T row by row
+// from the packed rows in LDS (the AND of row and vector, the XOR fold of
+// the products' words, the parity of the fold: the Theorem's log2 addition
+// tree over the row's support) and writes the syndrome bit-packed.
+__global__ __launch_bounds__(256) void pmult_batch_kernel(const uint32_t *h_rows, uint32_t rows,
+                                                          uint32_t w32, const uint64_t *x,
+                                                          uint32_t count, uint64_t *syn)
+{
+    extern __shared__ uint32_t hs[];
+    for (uint32_t i = threadIdx.x; i < rows * w32; i += blockDim.x)
+        hs[i] = h_rows[i];
+    __syncthreads();
+    const uint32_t w64 = w32 / 2, s64 = (rows + 63) / 64;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < count;
+         v += gridDim.x * blockDim.x) {
+        const uint32_t *xv = (const uint32_t *)(x + (uint64_t)v * w64);
+        uint64_t *out = syn + (uint64_t)v * s64;
+        for (uint32_t o = 0; o < s64; o++) {
+            uint64_t bits = 0;
+            for (uint32_t r = 64 * o; r < rows && r < 64 * (o + 1); r++) {
+                uint32_t acc = 0;
+                for (uint32_t k = 0; k < w32; k++)
+                    acc ^= hs[r * w32 + k] & xv[k];
+                bits |= (uint64_t)(__popc(acc) & 1u) << (r - 64 * o);
+            }
+            out[o] = bits;
+        }
     }
 }
 
 }  // namespace
 
-extern "C" int grand_probe_dense_pmult(const grand_code *code, uint32_t words,
-                                       uint32_t patterns, double *checks_per_s,
+extern "C" int grand_pmult(const grand_code *code, const uint64_t *x, uint32_t count,
+                           uint64_t *syndromes, void *stream)
+{
+    if (!code || (count && (!x || !syndromes)))
+        return GRAND_EINVAL;
+    if (count == 0)
+        return GRAND_OK;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != code->device ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return GRAND_EDEVICE;
+    const uint32_t lds = code->rows * code->row_w32 * 4u;
+    if (hipFuncSetAttribute((const void *)pmult_batch_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return GRAND_EDEVICE;
+    const uint32_t grid = std::min<uint32_t>((count + 255) / 256, (uint32_t)cus * 8u);
+    hipLaunchKernelGGL(pmult_batch_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream,
+                       code->d_rows, code->rows, code->row_w32, x, count, syndromes);
+    return hipGetLastError() == hipSuccess ? GRAND_OK : GRAND_EDEVICE;
+}
+
+extern "C" int grand_probe_dense_pmult(const grand_code *code, const uint64_t *words_dev,
+                                       uint32_t words, uint32_t patterns, double *checks_per_s,
                                        uint64_t *zero_syndromes)
 {
     if (!code || !checks_per_s || words == 0 || patterns == 0 || patterns > 65536 ||
@@ -154,7 +210,7 @@ extern "C" int grand_probe_dense_pmult(const grand_code *code, uint32_t words,
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         goto done;
     // warm-up on the first word's patterns, then the timed launch
-    rc = launch_dense_any(code, grid, patterns, patterns, zeros);
+    rc = launch_dense_any(code, grid, patterns, patterns, (const uint32_t *)words_dev, zeros);
     if (rc)
         goto done;
     rc = GRAND_EDEVICE;
@@ -162,7 +218,7 @@ extern "C" int grand_probe_dense_pmult(const grand_code *code, uint32_t words,
         hipMemset(zeros, 0, sizeof(unsigned long long)) != hipSuccess ||
         hipEventRecord(e0, 0) != hipSuccess)
         goto done;
-    rc = launch_dense_any(code, grid, checks, patterns, zeros);
+    rc = launch_dense_any(code, grid, checks, patterns, (const uint32_t *)words_dev, zeros);
     if (rc)
         goto done;
     rc = GRAND_EDEVICE;

@@ -84,7 +84,8 @@ struct grand_server {
     grand_server_config cfg;
     DeviceCtx *ctx = nullptr;
     std::mutex mu;
-    std::deque<Request> pending;
+    std::deque<Request> pending;      // requests for the ordinary lanes
+    std::deque<Request> pending_wide; // long words, for the wide lanes (if any)
     std::vector<std::unique_ptr<Lane>> lanes;
     std::deque<grand_result> done;
     uint64_t next_id = 1;
@@ -193,17 +194,18 @@ void lane_emit(grand_server *s, Lane &L, uint32_t i, double t)
     L.left--;
 }
 
-// Move pending requests (up to the lane's capacity) onto an idle lane and
-// launch them, heaviest first.
-int lane_launch(grand_server *s, Lane &L)
+// Move requests of `queue` (up to the lane's capacity) onto an idle lane and
+// launch them, heaviest first.  A wide lane gives every request one
+// 1024-thread workgroup.
+int lane_launch(grand_server *s, Lane &L, std::deque<Request> &queue, bool wide)
 {
-    const uint32_t B = (uint32_t)std::min<size_t>(s->pending.size(), L.cap);
+    const uint32_t B = (uint32_t)std::min<size_t>(queue.size(), L.cap);
     if (B == 0)
         return GRAND_OK;
     L.reqs.clear();
     for (uint32_t i = 0; i < B; i++) {
-        L.reqs.push_back(std::move(s->pending.front()));
-        s->pending.pop_front();
+        L.reqs.push_back(std::move(queue.front()));
+        queue.pop_front();
     }
     std::stable_sort(L.reqs.begin(), L.reqs.end(), [](const Request &x, const Request &y) {
         const uint32_t wx = items_pow2(x.code->n, x.M), wy = items_pow2(y.code->n, y.M);
@@ -220,7 +222,9 @@ int lane_launch(grand_server *s, Lane &L)
         std::memcpy(L.rx + (size_t)i * kSlotFloats, q.rx.data(), q.rx.size() * sizeof(float));
         ni = std::max(ni, items_pow2(c->n, q.M));
     }
-    const grand_tuning t = tuning_for(0, 0);
+    grand_tuning t = tuning_for(0, 0);
+    if (wide)
+        t.block = kMaxBlock;
     const uint32_t grid = std::max(1u, std::min(B, L.grid));
     L.seq = L.seq + 1 ? L.seq + 1 : 1;   // flags of this launch hold seq (never 0)
     KernelArgs a;
@@ -329,11 +333,14 @@ int submit_locked(grand_server *s, const grand_code *code, const float *rx, uint
     q.submit_s = now_s();
     q.arrival_s = arrival > 0 ? arrival : q.submit_s;
     q.bytes = bytes;
-    s->pending.push_back(std::move(q));
+    std::deque<Request> &queue =
+        s->cfg.wide_lanes && 2 * symbols(code->n, M) >= GRAND_WIDE_ITEMS ? s->pending_wide
+                                                                         : s->pending;
+    queue.push_back(std::move(q));
     s->inflight++;
     s->mem_in_use += bytes;
     if (id)
-        *id = s->pending.back().id;
+        *id = queue.back().id;
     return GRAND_OK;
 }
 
@@ -359,11 +366,12 @@ int poll_locked(grand_server *s, grand_result *out, uint32_t max_out, uint32_t *
         if (rc)
             return rc;
     }
-    for (auto &L : s->lanes) {
-        if (s->pending.empty())
-            break;
-        if (!L->busy) {
-            int rc = lane_launch(s, *L);
+    for (size_t k = 0; k < s->lanes.size(); k++) {
+        Lane &L = *s->lanes[k];
+        const bool wide = k < s->cfg.wide_lanes;
+        std::deque<Request> &queue = wide ? s->pending_wide : s->pending;
+        if (!L.busy && !queue.empty()) {
+            int rc = lane_launch(s, L, queue, wide);
             if (rc)
                 return rc;
         }
@@ -394,7 +402,8 @@ int grand_server_create(const grand_server_config *cfg, grand_server **out)
         return fail(GRAND_EINVAL, "persistent serving mode is not available");
     if (cfg->max_inflight < 1 || cfg->max_inflight > (1u << 20) || cfg->memory_budget == 0 ||
         cfg->mode != GRAND_SERVE_LANES || cfg->lanes < 1 || cfg->lanes > 32 ||
-        cfg->max_batch < 1 || cfg->max_batch > 65536)
+        cfg->max_batch < 1 || cfg->max_batch > 65536 || cfg->wide_lanes >= cfg->lanes ||
+        cfg->pad != 0)
         return fail(GRAND_EINVAL, "invalid server configuration");
     DeviceCtx *ctx;
     int rc = current_ctx(&ctx);
@@ -446,12 +455,14 @@ int grand_server_cancel(grand_server *s, uint64_t request_id)
     if (!s)
         return fail(GRAND_EINVAL, "null server");
     std::lock_guard<std::mutex> g(s->mu);
-    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
-        if (it->id == request_id) {
-            s->mem_in_use -= it->bytes;
-            s->inflight--;
-            s->pending.erase(it);
-            return GRAND_OK;
+    for (std::deque<Request> *queue : {&s->pending, &s->pending_wide}) {
+        for (auto it = queue->begin(); it != queue->end(); ++it) {
+            if (it->id == request_id) {
+                s->mem_in_use -= it->bytes;
+                s->inflight--;
+                queue->erase(it);
+                return GRAND_OK;
+            }
         }
     }
     return fail(GRAND_ENOTFOUND, "request not pending (unknown, launched or finished)");
@@ -472,7 +483,7 @@ int grand_server_stats(grand_server *s, uint64_t *pending, uint64_t *running,
         return fail(GRAND_EINVAL, "null server");
     std::lock_guard<std::mutex> g(s->mu);
     if (pending)
-        *pending = s->pending.size();
+        *pending = s->pending.size() + s->pending_wide.size();
     if (running)
         *running = s->running;
     if (memory_in_use)

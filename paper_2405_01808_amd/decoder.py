@@ -110,7 +110,7 @@ class BatchPlan:
     """Host metadata and device outputs of a batch, reusable across calls."""
 
     def __init__(self, codes, code_index, M, cap, noise_var, rx_offset, rx, device=None,
-                 cutoff: int = 0):
+                 cutoff: int = 0, launch_mode: int = 0):
         import torch
         self.codes = list(codes)
         self.count = len(code_index)
@@ -150,6 +150,7 @@ class BatchPlan:
         b.status_out = self.out.status.data_ptr()
         b.checks_out = self.out.checks.data_ptr()
         b.cutoff_symbols = int(cutoff)
+        b.launch_mode = int(launch_mode)   # 0 auto, 1 one merged launch, 2 one per (n, M)
         b.rx_count = self.rx.numel()
         self.desc = b
 
@@ -235,11 +236,35 @@ def probe_xor_rate(steps: int = 1 << 14) -> tuple[float, float]:
     return rate.value, sec.value
 
 
-def probe_dense_pmult(code: Code, words: int, patterns: int) -> tuple[float, int]:
+def probe_dense_pmult(code: Code, words: int, patterns: int, words_dev=None) -> tuple[float, int]:
     """Checks per second of one full Algorithm 1 product per pattern (the
     incremental syndrome's baseline), and the zero syndromes it found
-    (grand_probe_dense_pmult)."""
+    (grand_probe_dense_pmult).  words_dev: a device tensor of `words` hard
+    words (ceil(n/64) int64 each), or None for hash-generated words."""
     rate, zeros = ctypes.c_double(0), ctypes.c_uint64(0)
-    nat.check(nat.lib().grand_probe_dense_pmult(code.handle, int(words), int(patterns),
+    wp = None
+    if words_dev is not None:
+        if words_dev.numel() < words * ((code.n + 63) // 64):
+            raise ValueError("words_dev holds fewer than `words` words")
+        wp = ctypes.c_void_p(words_dev.data_ptr())
+    nat.check(nat.lib().grand_probe_dense_pmult(code.handle, wp, int(words), int(patterns),
                                                 ctypes.byref(rate), ctypes.byref(zeros)))
     return rate.value, zeros.value
+
+
+def pmult(code: Code, x, stream=None):
+    """Algorithm 1 on a batch (grand_pmult): x is a device int64 tensor of
+    shape (count, ceil(n/64)); returns the syndromes as a device int64 tensor
+    of shape (count, ceil(rows/64))."""
+    import torch
+    w64 = (code.n + 63) // 64
+    if x.dim() != 2 or x.shape[1] != w64 or x.dtype != torch.int64 or not x.is_cuda:
+        raise ValueError(f"x must be a CUDA int64 tensor of shape (count, {w64})")
+    x = x.contiguous()
+    out = torch.zeros((x.shape[0], (code.rows + 63) // 64), dtype=torch.int64, device=x.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    nat.check(nat.lib().grand_pmult(code.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sp)))
+    return out

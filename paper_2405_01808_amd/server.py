@@ -39,10 +39,11 @@ def request_bytes(n: int, M: int) -> int:
 
 class Server:
     def __init__(self, max_inflight=4096, lanes=4, max_batch=2048, memory_budget=8 << 30,
-                 persistent=False):
+                 persistent=False, wide_lanes=0):
         self._lib = nat.lib()
         mode = nat.SERVE_PERSISTENT if persistent else nat.SERVE_LANES
-        cfg = nat.GrandServerConfig(max_inflight, lanes, max_batch, mode, memory_budget)
+        cfg = nat.GrandServerConfig(max_inflight, lanes, max_batch, mode, memory_budget,
+                                    wide_lanes, 0)
         h = ctypes.c_void_p()
         nat.check(self._lib.grand_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -148,7 +148,9 @@ def test_dense_pmult_probe_rejects_bad_arguments_on_host():
     from paper_2405_01808_amd import _native as nat
     L = nat.lib()
     r = ctypes.c_double()
-    assert L.grand_probe_dense_pmult(None, 1, 1, ctypes.byref(r), None) == nat.GRAND_EINVAL
+    assert L.grand_probe_dense_pmult(None, None, 1, 1, ctypes.byref(r), None) == nat.GRAND_EINVAL
+    assert L.grand_pmult(None, None, 1, None, None) == nat.GRAND_EINVAL
+    assert L.grand_pmult(None, None, 0, None, None) == nat.GRAND_EINVAL
 
 
 def test_batch_shape_checks_on_host():

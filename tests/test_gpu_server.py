@@ -64,14 +64,17 @@ PERSISTENT_OFF = pytest.mark.skip(
            "(killed for silence) and the cause is not established")
 
 
-@pytest.mark.parametrize("persistent", [False, pytest.param(True, marks=PERSISTENT_OFF)],
-                         ids=["lanes", "persistent"])
-def test_mix_results_equal_single_decodes_and_oracle(gpu, persistent):
+@pytest.mark.parametrize("persistent,wide", [(False, 0), (False, 2),
+                                              pytest.param(True, 0, marks=PERSISTENT_OFF)],
+                         ids=["lanes", "wide_lanes", "persistent"])
+def test_mix_results_equal_single_decodes_and_oracle(gpu, persistent, wide):
+    """wide_lanes = 2: long words (2L >= 512) go to two lanes of their own,
+    one 1024-thread workgroup each; results are the same."""
     jobs = w.config_jobs("serving_mix", count=600, cap=1 << 14)
     codes = Codes(gpu)
     trace = make_trace(gpu, jobs, 5e4, codes)
-    srv = gpu.Server(max_inflight=256, lanes=4, max_batch=128, memory_budget=1 << 30,
-                     persistent=persistent)
+    srv = gpu.Server(max_inflight=256, lanes=4 + wide, max_batch=128, memory_budget=1 << 30,
+                     persistent=persistent, wide_lanes=wide)
     res, wall = trace.run_server(srv)
     srv.close()
     print(f"served {len(jobs)} requests in {wall * 1e3:.1f} ms", flush=True)
@@ -92,7 +95,8 @@ def test_serving_mix_at_full_cap_matches_oracle(gpu):
     assert all(j.cap == 1 << 18 for j in jobs)
     codes = Codes(gpu)
     trace = make_trace(gpu, jobs, 2e5, codes)
-    srv = gpu.Server(max_inflight=1024, lanes=4, max_batch=64, memory_budget=4 << 30)
+    srv = gpu.Server(max_inflight=1024, lanes=6, max_batch=64, memory_budget=4 << 30,
+                     wide_lanes=2)
     res, wall = trace.run_server(srv)
     srv.close()
     print(f"served {len(jobs)} requests at cap 2^18 in {wall * 1e3:.1f} ms", flush=True)

@@ -121,3 +121,29 @@ def jobs_from_spec(name: str, seed: int, count: int, cap: int, Ns, Ms, ebn0) -> 
     """An ad-hoc workload with the same recipe (used by tests for edge cases)."""
     spec = Spec(name, seed=seed, count=count, cap=cap, Ns=tuple(Ns), Ms=tuple(Ms), ebn0=ebn0)
     return make_jobs(spec, range(count))
+
+
+def _chunk(args):
+    name, start, count, cap = args
+    jobs = config_jobs(name, count=count, cap=cap, start=start)
+    return jobs
+
+
+def config_jobs_parallel(name: str, count: int | None = None, cap: int | None = None,
+                         start: int = 0, workers: int = 8) -> list[Job]:
+    """config_jobs over a process pool: the same Jobs (each word is a pure
+    function of its seed and index), generated in chunks."""
+    spec = CONFIGS[name]
+    n = spec.count if count is None else count
+    if workers <= 1 or n < 4096:
+        return config_jobs(name, count=n, cap=cap, start=start)
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    step = max(1024, -(-n // (4 * workers)))
+    parts = [(name, start + k, min(step, n - k), cap) for k in range(0, n, step)]
+    out: list[Job] = []
+    # fresh interpreters, not forks: the caller may have initialised a GPU
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        for jobs in ex.map(_chunk, parts):
+            out.extend(jobs)
+    return out

@@ -103,6 +103,29 @@ def encode(u_info: np.ndarray, N: int, info: list[int]) -> np.ndarray:
     return x
 
 
+def rref_basis(h_dense: np.ndarray) -> np.ndarray:
+    """Another basis of the same null space: the reduced row echelon form of
+    H over GF(2) (pivot columns from the left), the basis whose density
+    Section III's Table II reports.  An input for the decoder like H itself:
+    any basis gives the same decodes."""
+    A = (np.array(h_dense, dtype=np.uint8) & 1).copy()
+    r = 0
+    for c in range(A.shape[1]):
+        piv = np.nonzero(A[r:, c])[0]
+        if piv.size == 0:
+            continue
+        p = r + int(piv[0])
+        if p != r:
+            A[[r, p]] = A[[p, r]]
+        rows = np.nonzero(A[:, c])[0]
+        rows = rows[rows != r]
+        A[rows] ^= A[r]
+        r += 1
+        if r == A.shape[0]:
+            break
+    return A
+
+
 class PolarCode:
     """(N, K) polar code with the PW frozen set, plus its packed H."""
 
