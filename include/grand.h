@@ -214,7 +214,8 @@ int grand_decode_batch_noalloc(const grand_batch *batch, void *stream);
 /* over and over, e.g. a receiver's frames: one call per batch)        */
 /* ------------------------------------------------------------------ */
 
-/* grand_graph_create validates and plans `batch` exactly as
+/* Algorithm 2 for every codeword of a batch, recorded once and replayed.
+ * grand_graph_create validates and plans `batch` exactly as
  * grand_decode_batch does, copies its job table to the device, and records
  * the launches as a HIP graph.  Each launch in the graph is preceded by a
  * kernel that zeroes its work counter, so every replay starts from the same
@@ -319,7 +320,9 @@ int grand_server_create(const grand_server_config *cfg, grand_server **out);
 /* Waits for work on the device, then releases everything. */
 void grand_server_destroy(grand_server *server);
 
-/* Admit one request; rx (2L floats, host) is copied.  Returns GRAND_EBUSY,
+/* Admit one request: one Algorithm 2 decode (Section III) of one codeword,
+ * with the same result as grand_decode of the same input.  rx (2L floats,
+ * host) is copied.  Returns GRAND_EBUSY,
  * leaving no state, when the slot count or the memory budget would be
  * exceeded; GRAND_EINVAL for bad arguments (as grand_decode). */
 int grand_server_submit(grand_server *server, const grand_code *code, const float *rx,
