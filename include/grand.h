@@ -248,7 +248,7 @@ typedef struct {
     uint32_t band_growth;  /* each later band aims at growth x the patterns
                               checked so far (2..64) */
     uint32_t node_cap;     /* high-subset store entries per workgroup, held in
-                              device memory, 18 bytes each (64..2^22) */
+                              device memory, 16 bytes each (64..2^21) */
     uint32_t grid_per_cu;  /* resident workgroups per compute unit for batches */
 } grand_tuning;
 

@@ -97,7 +97,7 @@ bool valid_tuning(const grand_tuning &t)
 {
     if (t.low_bits > kMaxLowBits || t.block < 64 || t.block > kMaxBlock || t.block % 64 ||
         t.first_band < 1 || t.band_growth < 2 || t.band_growth > 64 || t.node_cap < 64 ||
-        t.node_cap > (1u << 22) || t.grid_per_cu < 1 || t.grid_per_cu > 32)
+        t.node_cap > (1u << 21) || t.grid_per_cu < 1 || t.grid_per_cu > 32)
         return false;
     if ((1u << t.low_bits) > kMergePer * t.block)   // merge outputs per thread
         return false;
@@ -273,7 +273,7 @@ size_t bucket_grids(DeviceCtx *ctx, const std::vector<Bucket> &buckets, std::vec
         uint32_t g = std::min<uint32_t>((uint32_t)buckets[i].words.size(),
                                         t.grid_per_cu * (uint32_t)ctx->cus);
         grids[i] = std::max(1u, g);
-        need = std::max<size_t>(need, (size_t)grids[i] * node_layout(t.node_cap).total);
+        need = std::max<size_t>(need, (size_t)grids[i] * node_bytes(t.node_cap));
     }
     return need;
 }

@@ -52,30 +52,16 @@ struct KernelArgs {
     uint64_t *checks_out; // may be null
     unsigned long long *queue;  // work counter; a launch takes indices from qbase on
     unsigned long long qbase;   // counter value at launch: ends at qbase + njobs + grid
-    uint8_t *scratch;     // grid x node_layout(node_cap).total bytes
+    uint8_t *scratch;     // grid x node_bytes(node_cap) bytes
     uint32_t *done_out;   // may be null: per-word completion flags (by output slot),
     uint32_t done_seq;    //   set to done_seq once the word's outputs are visible
     uint32_t pad2;
 };
 
-// Layout of one workgroup's high-subset store (byte offsets; 18 B/entry).
-struct NodeLayout {
-    uint64_t cost, lead, par, rl, ptr, cnext, total;
-};
-
-__host__ __device__ inline NodeLayout node_layout(uint32_t node_cap)
+// Bytes of one workgroup's high-subset store: a 16-byte record per node.
+__host__ __device__ inline uint64_t node_bytes(uint32_t node_cap)
 {
-    NodeLayout L;
-    auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
-    uint64_t o = 0;
-    L.cost = o; o = al(o + 4ull * node_cap);
-    L.lead = o; o = al(o + 4ull * node_cap);
-    L.par = o;  o = al(o + 4ull * node_cap);
-    L.rl = o;   o = al(o + 2ull * node_cap);
-    L.ptr = o;  o = al(o + 2ull * node_cap);
-    L.cnext = o; o = al(o + 2ull * node_cap);
-    L.total = o;
-    return L;
+    return 16ull * node_cap;
 }
 
 constexpr uint32_t kMergePer = 8;    // low-table merge outputs per thread and level

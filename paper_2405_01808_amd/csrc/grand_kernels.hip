@@ -87,14 +87,36 @@ struct Arr {
     uint32_t *lidx;    // bucket index of the low table
 };
 
-// Node store in the workgroup's HBM slot (structure of arrays).
+// Node store in the workgroup's HBM slot: one 16-byte record per node, so a
+// node is read or written whole with one instruction.
+//   x  cost of the high subset
+//   y  leading word of s(yhat) + its columns
+//   z  parent (bits 0-20; node 0, the empty subset, has none) | first child
+//      rank = own rank + 1 (b for node 0) << 21
+//   w  low-table entries already checked with this node (bits 0-15) | first
+//      child rank not yet in the store << 16; each half is also written alone
+constexpr uint32_t kParBits = 21;
+constexpr uint32_t kParMask = (1u << kParBits) - 1;
+
 struct Nodes {
-    uint32_t *cost;    // cost of the high subset
-    uint32_t *lead;    // leading word of s(yhat) + its columns
-    uint32_t *par;     // parent (kNone for the empty subset, node 0)
-    uint16_t *rl;      // first child rank = own rank + 1 (b for node 0)
-    uint16_t *ptr;     // low-table entries already checked with this node
-    uint16_t *cnext;   // first child rank not yet in the store
+    uint4 *rec;
+
+    __device__ uint32_t cost(uint32_t h) const { return rec[h].x; }
+    __device__ uint32_t par(uint32_t h) const { return rec[h].z & kParMask; }
+    __device__ uint32_t rl(uint32_t h) const { return rec[h].z >> kParBits; }
+    __device__ void set_ptr(uint32_t h, uint32_t v) const
+    {
+        reinterpret_cast<uint16_t *>(rec + h)[6] = (uint16_t)v;
+    }
+    __device__ void set_cnext(uint32_t h, uint32_t v) const
+    {
+        reinterpret_cast<uint16_t *>(rec + h)[7] = (uint16_t)v;
+    }
+    __device__ void set(uint32_t h, uint32_t c, uint32_t ld, uint32_t p, uint32_t r1,
+                        uint32_t pt, uint32_t cn) const
+    {
+        rec[h] = make_uint4(c, ld, (p & kParMask) | (r1 << kParBits), pt | (cn << 16));
+    }
 };
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -262,11 +284,12 @@ __device__ int colex_cmp(const Nodes &nd, uint32_t a, uint32_t b)
             return -1;
         if (b == 0)
             return 1;
-        uint32_t ra = nd.rl[a], rb = nd.rl[b];
+        const uint32_t za = nd.rec[a].z, zb = nd.rec[b].z;
+        const uint32_t ra = za >> kParBits, rb = zb >> kParBits;
         if (ra != rb)
             return ra < rb ? -1 : 1;
-        a = nd.par[a];
-        b = nd.par[b];
+        a = za & kParMask;
+        b = zb & kParMask;
     }
 }
 
@@ -289,8 +312,8 @@ __device__ bool full_zero(const Arr &A, const Nodes &nd, const DevCode &code,
     const uint32_t mask = lkey[l] & kMaskAll;
     for (uint32_t w = 1; w < kw; w++) {
         uint32_t acc = A.s0[w];
-        for (uint32_t x = h; x != 0; x = nd.par[x]) {
-            uint32_t p = A.ikey[nd.rl[x] - 1] & 1023u;
+        for (uint32_t x = h; x != 0; x = nd.par(x)) {
+            uint32_t p = A.ikey[nd.rl(x) - 1] & 1023u;
             acc ^= code.h_cols[(uint64_t)p * kw + w];
         }
         for (uint32_t m = mask; m; m &= m - 1)
@@ -432,9 +455,10 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
             {
                 const uint32_t h = pstart + wid * 64 + lane;
                 if (h < pend) {
-                    nx_c = nd.cost[h];
-                    nx_lo = first ? nd.cnext[h] : nd.rl[h];
-                    nx_ld = nd.lead[h];
+                    const uint4 v = nd.rec[h];
+                    nx_c = v.x;
+                    nx_lo = first ? v.w >> 16 : v.z >> kParBits;
+                    nx_ld = v.y;
                 }
             }
             for (uint32_t c0 = pstart + wid * 64; c0 < pend; c0 += wstride) {
@@ -442,9 +466,10 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
                 uint32_t cnt = 0, lead = 0;
                 const uint32_t ch = nx_c, lo = nx_lo, ld = nx_ld;
                 if (h + wstride < pend) {
-                    nx_c = nd.cost[h + wstride];
-                    nx_lo = first ? nd.cnext[h + wstride] : nd.rl[h + wstride];
-                    nx_ld = nd.lead[h + wstride];
+                    const uint4 v = nd.rec[h + wstride];
+                    nx_c = v.x;
+                    nx_lo = first ? v.w >> 16 : v.z >> kParBits;
+                    nx_ld = v.y;
                 }
                 if (h < pend && lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
                     lead = ld;
@@ -461,7 +486,7 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
                 // ends in a roll-back
                 const bool fits = (uint64_t)base + total <= node_cap;
                 if (h < pend && (cnt || !first))
-                    nd.cnext[h] = (uint16_t)(lo + cnt);
+                    nd.set_cnext(h, lo + cnt);
                 if (!total || !fits)
                     continue;
                 wave_sync();   // the previous block's children are written
@@ -480,13 +505,8 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
                     if (j >= 64)
                         k = flat_owner(S.foff, k, ncnt, j);
                     const uint32_t r = S.fb[k] + (j - S.foff[k]);
-                    const uint32_t dst = base + j;
-                    nd.cost[dst] = S.fcost[k] + (A.ikey[r] >> 10);
-                    nd.lead[dst] = S.flead[k] ^ A.col0[r];
-                    nd.par[dst] = S.fa[k];
-                    nd.rl[dst] = (uint16_t)(r + 1);
-                    nd.ptr[dst] = 0;
-                    nd.cnext[dst] = (uint16_t)(r + 1);
+                    nd.set(base + j, S.fcost[k] + (A.ikey[r] >> 10), S.flead[k] ^ A.col0[r],
+                           S.fa[k], r + 1, 0, r + 1);
                 }
             }
             // the pass's children are the next pass's parents
@@ -509,7 +529,7 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
         }
         // roll back: drop the new nodes and restore the old child frontiers
         for (uint32_t h = tid; h < used0; h += bs)
-            nd.cnext[h] = (uint16_t)child_end(A.ikey, ibk, nd.rl[h], n, kE, (int32_t)nd.cost[h]);
+            nd.set_cnext(h, child_end(A.ikey, ibk, nd.rl(h), n, kE, (int32_t)nd.cost(h)));
         __syncthreads();
         const int64_t vE = thr_lin(kE, n), vn = thr_lin(kn, n);
         if (vn - vE <= 1) {
@@ -570,12 +590,7 @@ __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint3
     }
     __syncthreads();   // also makes s(yhat) and the leading words visible
     if (tid == 0) {
-        nd.cost[0] = 0;
-        nd.lead[0] = A.s0[0];
-        nd.par[0] = kNone;
-        nd.rl[0] = (uint16_t)b;
-        nd.ptr[0] = 0;
-        nd.cnext[0] = (uint16_t)b;
+        nd.set(0, 0, A.s0[0], 0, b, 0, b);
     }
     // XOR over every subset of the lower and of the upper half of the b
     // flips' leading words, behind the merge buffer
@@ -895,10 +910,11 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         uint32_t nx_ptr = 0, nx_cost = 0, nx_lead = 0, nx_rl = 0;
         if (wid * 64 + lane < used) {
             const uint32_t h = wid * 64 + lane;
-            nx_ptr = nd.ptr[h];
-            nx_cost = nd.cost[h];
-            nx_lead = nd.lead[h];
-            nx_rl = nd.rl[h];
+            const uint4 v = nd.rec[h];
+            nx_ptr = v.w & 0xFFFFu;
+            nx_cost = v.x;
+            nx_lead = v.y;
+            nx_rl = v.z >> kParBits;
         }
         for (uint32_t c0 = wid * 64; c0 < used;) {
             const uint32_t h = c0 + lane;
@@ -913,15 +929,16 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                 uint32_t hi = node_end(lkey, lbk, LB, kt, (int32_t)ch, h, rl, lo);
                 if (hi > lo) {
                     cnt = hi - lo;
-                    nd.ptr[h] = (uint16_t)hi;
+                    nd.set_ptr(h, hi);
                 }
             }
             cn = (uint32_t)__builtin_amdgcn_readlane((int)cn, 0);
             if (cn + lane < used) {
-                nx_ptr = nd.ptr[cn + lane];
-                nx_cost = nd.cost[cn + lane];
-                nx_lead = nd.lead[cn + lane];
-                nx_rl = nd.rl[cn + lane];
+                const uint4 v = nd.rec[cn + lane];
+                nx_ptr = v.w & 0xFFFFu;
+                nx_cost = v.x;
+                nx_lead = v.y;
+                nx_rl = v.z >> kParBits;
             }
             const uint32_t xs = wave_incl_scan(cnt);
             const uint32_t off = xs - cnt;
@@ -1038,7 +1055,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             __syncthreads();
             unsigned long long below = 0;
             for (uint32_t h = tid; h < used; h += bs) {
-                int32_t ch = (int32_t)nd.cost[h];
+                int32_t ch = (int32_t)nd.cost(h);
                 if (ch > (int32_t)hc)
                     continue;
                 uint32_t lo = ub_bucket(lkey, lbk, kMaskBits, 1ll << 19, 0, LB, (int64_t)hc - 1 - ch);
@@ -1095,8 +1112,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         for (uint32_t w = 0; w < kMaxN / 32; w++)
             flips[w] = 0;
         if (found) {
-            for (uint32_t h = hit_h; h != 0; h = nd.par[h]) {
-                uint32_t p = A.ikey[nd.rl[h] - 1] & 1023u;
+            for (uint32_t h = hit_h; h != 0; h = nd.par(h)) {
+                uint32_t p = A.ikey[nd.rl(h) - 1] & 1023u;
                 flips[p >> 5] ^= 1u << (p & 31u);
             }
             for (uint32_t msk = lkey[hit_l] & kMaskAll; msk; msk &= msk - 1) {
@@ -1149,14 +1166,7 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
     w.lkey = dyn + ly.lkey;
     w.ltmp = dyn + ly.ltmp;
     w.ls0 = dyn + ly.ls0;
-    const NodeLayout lay = node_layout(a.node_cap);
-    uint8_t *slot = a.scratch + (uint64_t)blockIdx.x * lay.total;
-    w.nd.cost = (uint32_t *)(slot + lay.cost);
-    w.nd.lead = (uint32_t *)(slot + lay.lead);
-    w.nd.par = (uint32_t *)(slot + lay.par);
-    w.nd.rl = (uint16_t *)(slot + lay.rl);
-    w.nd.ptr = (uint16_t *)(slot + lay.ptr);
-    w.nd.cnext = (uint16_t *)(slot + lay.cnext);
+    w.nd.rec = (uint4 *)(a.scratch + (uint64_t)blockIdx.x * node_bytes(a.node_cap));
     return w;
 }
 

@@ -144,7 +144,7 @@ extern "C" int grand_decode_batch_noalloc(const grand_batch *b, void *stream)
         return rc;
     grand_tuning t = tuning_for(0, 0);
     t.node_cap = kNoAllocNodeCap;
-    const uint64_t slot = node_layout(t.node_cap).total;
+    const uint64_t slot = node_bytes(t.node_cap);
     const uint64_t slots = (GRAND_NOALLOC_SCRATCH_BYTES - kNodesOff) / slot;
     uint32_t grid = std::min<uint32_t>(b->count, t.grid_per_cu * (uint32_t)ctx->cus);
     grid = (uint32_t)std::min<uint64_t>(grid, slots);

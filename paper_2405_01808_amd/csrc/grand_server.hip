@@ -128,7 +128,7 @@ int lane_init(Lane &L, uint32_t cap, uint32_t grid)
         return rc;
     if ((rc = init_stream_res(L.res)))
         return rc;
-    return ensure_scratch(L.res, (size_t)grid * node_layout(tuning_for(0, 0).node_cap).total);
+    return ensure_scratch(L.res, (size_t)grid * node_bytes(tuning_for(0, 0).node_cap));
 }
 
 void lane_free(Lane &L)
@@ -391,7 +391,7 @@ uint64_t grand_request_bytes(uint32_t n, uint32_t M)
         return 0;
     const grand_tuning t = tuning_for(n, M);
     return 2ull * symbols(n, M) * sizeof(float) + (kCwStride + 3) * 8 +
-           node_layout(t.node_cap).total;
+           node_bytes(t.node_cap);
 }
 
 int grand_server_create(const grand_server_config *cfg, grand_server **out)

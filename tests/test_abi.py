@@ -119,7 +119,7 @@ def test_request_bytes_reflects_tuned_store():
     assert nat.lib().grand_request_bytes(32, 8) == 0
     b = g.request_bytes(1024, 4)
     t = g.get_tuning(1024, 4)
-    assert b > 18 * t["node_cap"]
+    assert b > 16 * t["node_cap"]
 
 
 def test_graph_calls_rejected_on_host():
