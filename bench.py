@@ -568,6 +568,9 @@ def main():
     ap.add_argument("--pipeline-streams", type=int, default=2)
     ap.add_argument("--no-xor-probe", dest="xor_probe", action="store_false",
                     help="skip the measured bitwise peak (grand_probe_xor_rate)")
+    ap.add_argument("--uneven-only", type=int, default=0, metavar="REPS",
+                    help="only time REPS replays of the uneven batch's merged launch (no "
+                         "autotuning) and print its JSON line (for profiling that launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB three times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -581,6 +584,22 @@ def main():
     # lane's launches run side by side (read by HIP when it initialises)
     os.environ["GPU_MAX_HW_QUEUES"] = HW_QUEUES
     import workload as w
+    if args.uneven_only:
+        ujobs = w.config_jobs_parallel("uneven_mix", workers=workers())
+        import torch
+        import paper_2405_01808_amd as g
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        g.init(0)
+        plan, _ = device_batch(g, ujobs)
+        graph = g.BatchGraph(plan)
+        ms = time_launches(graph.launch, args.uneven_only, torch.cuda.current_stream())
+        q = plan.out.queries.cpu().numpy().view(np.uint64)[:len(ujobs)].astype(np.float64)
+        graph.close()
+        print(json.dumps({"workload": "uneven_mix merged launch (graph replay)", "reps":
+                          args.uneven_only, "ms_per_launch": ms,
+                          "useful_checks_per_s": q.sum() / (ms / 1e3),
+                          "roofline": uneven_roofline(ujobs, q, ms)}), flush=True)
+        return
     # inputs first, before anything touches the GPU
     t0 = time.time()
     nwk = workers()
