@@ -75,8 +75,16 @@ constexpr uint32_t kBucketsPerKey = 1;  // cost buckets per sorted key
 // low table (keys and leading syndrome words, 2^b each).
 struct LdsLayout {
     uint32_t yhat, s0, ikey, col0, lcol, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
-        ltmp, ls0, words;
+        ltmp, ls0, lfilt, words;
 };
+
+// Bits of the low table's leading-word filter: 32 per entry up to 2^11
+// entries (a one-hash bitmap, ~3 % false positives at that load), 2^16 for
+// larger tables.
+__host__ __device__ inline uint32_t filter_log2(uint32_t low_bits)
+{
+    return (low_bits < 11 ? low_bits : 11) + 5;
+}
 
 __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uint32_t low_bits)
 {
@@ -111,6 +119,7 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.lkey = o;  o += 1u << low_bits;
     o = (o + 3) & ~3u;          // 16-byte alignment of the leading words
     L.ls0 = o;   o += (1u << low_bits) + 8;   // padded for 8-wide reads
+    L.lfilt = o; o += 1u << (filter_log2(low_bits) - 5);
     L.words = o;
     return L;
 }

@@ -29,8 +29,10 @@
 //     thresholds that each admit a prefix of the (cost, colex) order (a
 //     whole cost level, or part of one when a level is too large).  For a
 //     fixed node the band's low entries form one contiguous range of the
-//     sorted table; the ranges of a block of nodes are laid end to end and
-//     cut into equal runs, one per thread.  The lowest (cost, colex) zero
+//     sorted table, and one of them can have a zero syndrome only if its
+//     leading word equals the node's: a bitmap filter of the table's
+//     leading words rules out most nodes with one LDS read, and the rest
+//     compare their range entry by entry.  The lowest (cost, colex) zero
 //     syndrome of the first band that has one is the answer; its 1-based
 //     rank q is counted exactly from the same sorted structures.  The search
 //     abandons when the bands cover the query cap.
@@ -65,14 +67,15 @@ struct Shared {
     uint32_t next;                   // next block of the check loop to take
 };
 
-// Per-slot staging of one block of nodes (one slot per thread).
+// Per-slot staging of one block of parents during an expansion pass (one
+// slot per thread).
 struct Stage {
-    uint32_t *foff;    // flat offsets of the slots' ranges
-    uint32_t *fa;      // node of each slot
-    uint32_t *fb;      // first rank / low index of each slot
-    uint32_t *fcost;   // cost of each slot's node
-    uint32_t *flead;   // leading syndrome word of each slot's node
-    uint32_t *fown;    // slot that owns the first entry of each thread's run
+    uint32_t *foff;    // flat offsets of the slots' child ranges
+    uint32_t *fa;      // parent node of each slot
+    uint32_t *fb;      // first child rank of each slot
+    uint32_t *fcost;   // cost of each slot's parent
+    uint32_t *flead;   // leading syndrome word of each slot's parent
+    uint32_t *fown;    // slot of child j, for the block's first 64 children
 };
 
 // Per-workgroup arrays in dynamic LDS, sized for the launch (lds_layout).
@@ -85,7 +88,15 @@ struct Arr {
     Stage st;          // staging of a block, 64 slots per wave
     uint32_t *iidx;    // bucket index of the ranked flips
     uint32_t *lidx;    // bucket index of the low table
+    uint32_t *lfilt;   // bitmap filter of the low table's leading words
 };
+
+// Bit of leading word x in the low table's filter of 2^fbits bits (a
+// multiplicative hash: its top bits depend on every bit of x).
+__device__ inline uint32_t filt_bit(uint32_t x, uint32_t fbits)
+{
+    return (x * 0x9E3779B1u) >> (32u - fbits);
+}
 
 // Node store in the workgroup's HBM slot: one 16-byte record per node, so a
 // node is read or written whole with one instruction.
@@ -560,7 +571,8 @@ __device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t 
 
 // Low table: the 2^b subsets of the b cheapest flips as keys cost <<
 // kMaskBits | mask, ascending (cost, then colex, which is the mask's integer
-// order), with their leading syndrome words.  The subsets of the first b0 =
+// order), with their leading syndrome words and a bitmap filter of those
+// words (one bit each, by filt_bit).  The subsets of the first b0 =
 // min(b, 6) flips are ranked in wave 0's registers: lane l holds subset l
 // and counts the smaller keys with readlane, with no LDS round trip.  Each
 // further flip j then merges the table with itself plus flip j (levels
@@ -588,6 +600,9 @@ __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint3
         if (tid < n0)
             src[r] = key;
     }
+    const uint32_t fbits = filter_log2(b);
+    for (uint32_t i = tid; i < (1u << (fbits - 5)); i += bs)
+        A.lfilt[i] = 0;
     __syncthreads();   // also makes s(yhat) and the leading words visible
     if (tid == 0) {
         nd.set(0, 0, A.s0[0], 0, b, 0, b);
@@ -637,7 +652,10 @@ __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint3
         __syncthreads();   // the subset tables
     for (uint32_t i = tid; i < LB; i += bs) {
         const uint32_t msk = lkey[i] & kMaskAll;
-        ls0[i] = sub[msk & (nlo - 1)] ^ sub[nlo + (msk >> blo)];
+        const uint32_t x = sub[msk & (nlo - 1)] ^ sub[nlo + (msk >> blo)];
+        ls0[i] = x;
+        const uint32_t fb = filt_bit(x, fbits);
+        atomicOr(&A.lfilt[fb >> 5], 1u << (fb & 31u));
     }
 }
 
@@ -893,18 +911,19 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
 
         // checks.  Each wave takes blocks of 64 nodes on its own (its first
         // by its index, the others from a shared counter), with no workgroup
-        // barrier until the band ends: the block's ranges
-        // are laid end to end (a wave scan) and cut into one run of
-        // consecutive (node, entry) pairs per lane; each piece of a run that
-        // belongs to one node is a tight comparison loop.
+        // barrier until the band ends; each lane takes one node of the
+        // block.  Pattern (node, entry) has a zero leading syndrome word iff
+        // the entry's leading word equals the node's, so a node whose word
+        // is not in the low table's filter has no candidate in its whole
+        // range; the others (the filter's false positives and the real
+        // matches) compare their range entry by entry.
         LaneHit best{0xFFFFFFFFu, kNone, 0};
         // (the wave index is uniform in a wave: readfirstlane keeps the
         // loop's bookkeeping in scalar registers)
         const uint32_t lane = lane_id(), nwv = bs >> 6;
         const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
-        const Stage S = Stage{A.st.foff + wid * 64, A.st.fa + wid * 64, A.st.fb + wid * 64,
-                              A.st.fcost + wid * 64, A.st.flead + wid * 64, A.st.fown + wid * 64};
-        unsigned long long wave_size = 0;
+        const uint32_t fbits = filter_log2(b);
+        uint32_t lane_size = 0;
         // the node fields of this lane's slot in the wave's next block are
         // loaded while the current block is processed
         uint32_t nx_ptr = 0, nx_cost = 0, nx_lead = 0, nx_rl = 0;
@@ -918,8 +937,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         }
         for (uint32_t c0 = wid * 64; c0 < used;) {
             const uint32_t h = c0 + lane;
-            uint32_t lo = nx_ptr, ch = nx_cost, lead = nx_lead, cnt = 0;
-            const uint32_t rl = nx_rl;
+            const uint32_t lo = nx_ptr, ch = nx_cost, ld = nx_lead, rl = nx_rl;
+            uint32_t cnt = 0;
             // the wave's next block comes from a shared counter, so waves
             // that finish early take more blocks
             uint32_t cn = 0;
@@ -940,68 +959,38 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                 nx_lead = v.y;
                 nx_rl = v.z >> kParBits;
             }
-            const uint32_t xs = wave_incl_scan(cnt);
-            const uint32_t off = xs - cnt;
-            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)xs, 63);
-            // slots with entries: a run steps from one to the next without
-            // reading the empty ones between
-            const unsigned long long nz = __ballot(cnt != 0);
-            wave_sync();   // the previous block's runs are done with the staging
-            S.fa[lane] = h;
-            S.fb[lane] = lo;
-            S.fcost[lane] = ch;
-            S.flead[lane] = lead;
-            S.foff[lane] = off;
-            // runs of `run` entries, one per lane; the slot holding a run's
-            // first entry records itself as that run's owner
-            const uint32_t run = (total + 63) >> 6;
+            lane_size += cnt;
             if (cnt) {
-                for (uint32_t t = (off + run - 1) / run; t * run < off + cnt; t++)
-                    S.fown[t] = lane;
-            }
-            wave_sync();
-            wave_size += total;
-            uint32_t j = lane * run;
-            const uint32_t jend = min(total, j + run);
-            if (j < jend) {
-                uint32_t k = S.fown[lane];
-                while (j < jend) {
-                    const unsigned long long later = k < 63 ? nz >> (k + 1) << (k + 1) : 0ull;
-                    const uint32_t kn = later ? (uint32_t)__builtin_ctzll(later) : 64u;
-                    const uint32_t kend = kn < 64 ? S.foff[kn] : total;
-                    const uint32_t e = min(jend, kend);
-                    const uint32_t l0 = S.fb[k] + (j - S.foff[k]);
-                    const uint32_t cntk = e - j;
-                    const uint32_t ld = S.flead[k];
+                const uint32_t fb = filt_bit(ld, fbits);
+                if ((A.lfilt[fb >> 5] >> (fb & 31u)) & 1u) {
                     // min over (entry XOR lead) is zero iff a leading word
                     // matches.  Reads start at the 16-byte boundary below
-                    // the piece and may run up to 7 entries past it (the
+                    // the range and may run up to 7 entries past it (the
                     // table is aligned and padded): an entry outside the
-                    // piece can only cause a spurious rescan below.
+                    // range can only cause a spurious rescan below.
                     uint32_t mn = 0xFFFFFFFFu;
-                    const uint32_t e0 = l0 + cntk;
-                    const uint4 *p4 = reinterpret_cast<const uint4 *>(ls0 + (l0 & ~3u));
-                    for (uint32_t t = l0 & ~3u; t < e0; t += 8, p4 += 2) {
+                    const uint32_t e0 = lo + cnt;
+                    const uint4 *p4 = reinterpret_cast<const uint4 *>(ls0 + (lo & ~3u));
+                    for (uint32_t t = lo & ~3u; t < e0; t += 8, p4 += 2) {
                         const uint4 x = p4[0], y = p4[1];
                         mn = min(mn, min(min(x.x ^ ld, x.y ^ ld), min(x.z ^ ld, x.w ^ ld)));
                         mn = min(mn, min(min(y.x ^ ld, y.y ^ ld), min(y.z ^ ld, y.w ^ ld)));
                     }
-                    const bool any = mn == 0;
-                    if (any) {   // a leading word matched: verify and keep the best
-                        const uint32_t node = S.fa[k], nc = S.fcost[k];
-                        for (uint32_t t = 0; t < cntk; t++)
-                            if (ls0[l0 + t] == ld && full_zero(A, nd, code, lkey, node, l0 + t))
-                                keep_best(best, nd, lkey, nc + (lkey[l0 + t] >> kMaskBits), node,
-                                          l0 + t);
+                    if (mn == 0) {   // a leading word matched: verify and keep the best
+                        for (uint32_t t = lo; t < e0; t++)
+                            if (ls0[t] == ld && full_zero(A, nd, code, lkey, h, t))
+                                keep_best(best, nd, lkey, ch + (lkey[t] >> kMaskBits), h, t);
                     }
-                    j = e;
-                    k = kn;   // the next piece, if any, is the next slot's
                 }
             }
             c0 = cn;
         }
-        if (lane == 0)
-            sh.wband[wid] = wave_size;
+        {   // the wave's sum (a lane's sum is below 2^28, the wave's may not be)
+            const uint32_t sl = wave_incl_scan(lane_size & 0xFFFFu);
+            const uint32_t sh16 = wave_incl_scan(lane_size >> 16);
+            if (lane == 63)
+                sh.wband[wid] = ((unsigned long long)sh16 << 16) + sl;
+        }
 
         // best hit of the band across the workgroup
         if (tid == 0)
@@ -1163,6 +1152,7 @@ __device__ inline Workspace workspace(const KernelArgs &a, uint32_t *dyn)
                    dyn + ly.fown};
     w.A.iidx = dyn + ly.iidx;
     w.A.lidx = dyn + ly.lidx;
+    w.A.lfilt = dyn + ly.lfilt;
     w.lkey = dyn + ly.lkey;
     w.ltmp = dyn + ly.ltmp;
     w.ls0 = dyn + ly.ls0;

@@ -11,6 +11,7 @@
 //     leading words padded for the comparison loop's reads (up to 7 entries
 //     past the end, from a 4-entry boundary);
 //   - the bucket indexes hold nb + 2 entries (nb = keys, read at nb + 1);
+//   - the leading-word filter holds 2^filter_log2(b) bits;
 //   - the merge of the low table gives each thread at most kMergePer outputs
 //     when the host accepts the tuning, and every accepted shape fits in the
 //     160 KiB of LDS a compute unit has.
@@ -62,7 +63,8 @@ int main()
                     {"staging", L.foff, staging_end - L.foff},
                     {"iidx", L.iidx, kBucketsPerKey * ni + 2},
                     {"lidx", L.lidx, kBucketsPerKey * LB + 2},
-                    {"lkey", L.lkey, LB}, {"ls0", L.ls0, LB + 8}};
+                    {"lkey", L.lkey, LB}, {"ls0", L.ls0, LB + 8},
+                    {"lfilt", L.lfilt, 1u << (filter_log2(b) - 5)}};
                 for (const Region &r : live)
                     EXPECT(r.off + r.len <= L.words);
                 for (size_t i = 0; i < live.size(); i++)
@@ -90,7 +92,10 @@ int main()
                 // the comparison loop reads 8 entries from t = (l0 & ~3) + 8k
                 // while t < l0 + cnt <= LB, so up to entry LB + 6: the leading
                 // words' allocation must reach that far
-                EXPECT(L.words - L.ls0 >= LB + 7);
+                EXPECT(L.lfilt - L.ls0 >= LB + 7);
+                // the leading-word filter: filt_bit gives filter_log2(b)
+                // bits, so word fb >> 5 lies in the filter
+                EXPECT(filter_log2(b) >= 5 && filter_log2(b) <= 32);
             }
         }
     }
