@@ -69,10 +69,11 @@ constexpr uint32_t kBucketsPerKey = 1;  // cost buckets per sorted key
 
 // Dynamic LDS of the decode kernel, in 32-bit words: the hard word and its
 // syndrome, the ranked flips and their columns' leading words (ni each),
-// the low flips' columns, per-slot staging of a block of nodes (one slot per
-// thread, with run owners; the low table is built in it before the bands
-// start), bucket indexes of the ranked flips and of the low table, and the
-// low table (keys and leading syndrome words, 2^b each).
+// the low flips' columns, per-slot staging of a block of parents in an
+// expansion pass (one slot per thread; the low table is built in it before
+// the bands start), bucket indexes of the ranked flips and of the low table,
+// the low table (keys and leading syndrome words, 2^b each) and the bitmap
+// filter of its leading words.
 struct LdsLayout {
     uint32_t yhat, s0, ikey, col0, lcol, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
         ltmp, ls0, lfilt, words;
@@ -117,8 +118,7 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t ni, uint32_t block, uin
     L.lidx = o;  o += kBucketsPerKey * (1u << low_bits) + 2;
     o = (o + 1) & ~1u;          // 8-byte alignment of the table
     L.lkey = o;  o += 1u << low_bits;
-    o = (o + 3) & ~3u;          // 16-byte alignment of the leading words
-    L.ls0 = o;   o += (1u << low_bits) + 8;   // padded for 8-wide reads
+    L.ls0 = o;   o += 1u << low_bits;
     L.lfilt = o; o += 1u << (filter_log2(low_bits) - 5);
     L.words = o;
     return L;

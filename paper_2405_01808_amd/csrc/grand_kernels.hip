@@ -960,27 +960,26 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                 nx_rl = v.z >> kParBits;
             }
             lane_size += cnt;
+            bool cand = false;
             if (cnt) {
                 const uint32_t fb = filt_bit(ld, fbits);
-                if ((A.lfilt[fb >> 5] >> (fb & 31u)) & 1u) {
-                    // min over (entry XOR lead) is zero iff a leading word
-                    // matches.  Reads start at the 16-byte boundary below
-                    // the range and may run up to 7 entries past it (the
-                    // table is aligned and padded): an entry outside the
-                    // range can only cause a spurious rescan below.
-                    uint32_t mn = 0xFFFFFFFFu;
-                    const uint32_t e0 = lo + cnt;
-                    const uint4 *p4 = reinterpret_cast<const uint4 *>(ls0 + (lo & ~3u));
-                    for (uint32_t t = lo & ~3u; t < e0; t += 8, p4 += 2) {
-                        const uint4 x = p4[0], y = p4[1];
-                        mn = min(mn, min(min(x.x ^ ld, x.y ^ ld), min(x.z ^ ld, x.w ^ ld)));
-                        mn = min(mn, min(min(y.x ^ ld, y.y ^ ld), min(y.z ^ ld, y.w ^ ld)));
-                    }
-                    if (mn == 0) {   // a leading word matched: verify and keep the best
-                        for (uint32_t t = lo; t < e0; t++)
-                            if (ls0[t] == ld && full_zero(A, nd, code, lkey, h, t))
-                                keep_best(best, nd, lkey, ch + (lkey[t] >> kMaskBits), h, t);
-                    }
+                cand = (A.lfilt[fb >> 5] >> (fb & 31u)) & 1u;
+            }
+            // the filter's hits (false positives and real matches, a few per
+            // block): the whole wave compares each one's range, 64 entries
+            // per step, and verifies the entries whose leading words match
+            for (unsigned long long cm = __ballot(cand); cm; cm &= cm - 1) {
+                const int k = __builtin_ctzll(cm);
+                const uint32_t kh = (uint32_t)__builtin_amdgcn_readlane((int)h, k);
+                const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)lo, k);
+                const uint32_t kcnt = (uint32_t)__builtin_amdgcn_readlane((int)cnt, k);
+                const uint32_t kld = (uint32_t)__builtin_amdgcn_readlane((int)ld, k);
+                const uint32_t kch = (uint32_t)__builtin_amdgcn_readlane((int)ch, k);
+                for (uint32_t t0 = 0; t0 < kcnt; t0 += 64) {
+                    const uint32_t t = klo + t0 + lane;
+                    if (t0 + lane < kcnt && ls0[t] == kld &&
+                        full_zero(A, nd, code, lkey, kh, t))
+                        keep_best(best, nd, lkey, kch + (lkey[t] >> kMaskBits), kh, t);
                 }
             }
             c0 = cn;

@@ -7,9 +7,7 @@
 //   - the overlays of the staging set hold what is built in them: the low
 //     table's build buffer and its two subset-XOR tables, and the symbol
 //     scores of the cut-off (ni words);
-//   - the low table is 8-byte and its leading words 16-byte aligned, with the
-//     leading words padded for the comparison loop's reads (up to 7 entries
-//     past the end, from a 4-entry boundary);
+//   - the low table is 8-byte aligned;
 //   - the bucket indexes hold nb + 2 entries (nb = keys, read at nb + 1);
 //   - the leading-word filter holds 2^filter_log2(b) bits;
 //   - the merge of the low table gives each thread at most kMergePer outputs
@@ -63,7 +61,7 @@ int main()
                     {"staging", L.foff, staging_end - L.foff},
                     {"iidx", L.iidx, kBucketsPerKey * ni + 2},
                     {"lidx", L.lidx, kBucketsPerKey * LB + 2},
-                    {"lkey", L.lkey, LB}, {"ls0", L.ls0, LB + 8},
+                    {"lkey", L.lkey, LB}, {"ls0", L.ls0, LB},
                     {"lfilt", L.lfilt, 1u << (filter_log2(b) - 5)}};
                 for (const Region &r : live)
                     EXPECT(r.off + r.len <= L.words);
@@ -86,13 +84,8 @@ int main()
                 EXPECT(L.ltmp == L.foff);
                 EXPECT(L.ltmp + lt <= staging_end);
                 EXPECT(L.ltmp + ni <= staging_end);   // the cut-off's symbol scores
-                // alignment and padding of the low table
+                // alignment of the low table
                 EXPECT(L.lkey % 2 == 0);
-                EXPECT(L.ls0 % 4 == 0);
-                // the comparison loop reads 8 entries from t = (l0 & ~3) + 8k
-                // while t < l0 + cnt <= LB, so up to entry LB + 6: the leading
-                // words' allocation must reach that far
-                EXPECT(L.lfilt - L.ls0 >= LB + 7);
                 // the leading-word filter: filt_bit gives filter_log2(b)
                 // bits, so word fb >> 5 lies in the filter
                 EXPECT(filter_log2(b) >= 5 && filter_log2(b) <= 32);
