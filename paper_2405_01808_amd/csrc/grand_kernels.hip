@@ -65,6 +65,7 @@ struct Shared {
     unsigned long long wband[kMaxBlock / 64];   // each wave's checks in the band
     uint32_t alloc;                  // node slots claimed in the current expansion
     uint32_t next;                   // next block of the check loop to take
+    uint32_t fertile[2];             // by pass parity: a child created may have children
 };
 
 // Per-slot staging of one block of parents during an expansion pass (one
@@ -453,10 +454,12 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
     const uint32_t used0 = sh.used;
     Thr kn = kwant;
     for (;;) {
-        if (tid == 0)
+        if (tid == 0) {
             sh.alloc = used0;
+            sh.fertile[0] = 0;
+        }
         __syncthreads();
-        uint32_t pstart = 0, pend = used0;
+        uint32_t pstart = 0, pend = used0, par = 0;
         bool first = true;
         for (;;) {   // one pass per forest level
             // the parent fields of this lane's slot in the wave's next block
@@ -512,23 +515,33 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
                 wave_sync();
                 const uint32_t ncnt = min(64u, pend - c0);
                 uint32_t k = lane < total ? S.fown[lane] : 0;
+                bool fert = false;
                 for (uint32_t j = lane; j < total; j += 64) {
                     if (j >= 64)
                         k = flat_owner(S.foff, k, ncnt, j);
                     const uint32_t r = S.fb[k] + (j - S.foff[k]);
-                    nd.set(base + j, S.fcost[k] + (A.ikey[r] >> 10), S.flead[k] ^ A.col0[r],
-                           S.fa[k], r + 1, 0, r + 1);
+                    const uint32_t cc = S.fcost[k] + (A.ikey[r] >> 10);
+                    nd.set(base + j, cc, S.flead[k] ^ A.col0[r], S.fa[k], r + 1, 0, r + 1);
+                    // the next pass tests this child as a parent the same way
+                    fert |= r + 1 < n && child_admitted(A.ikey, r + 1, kn, (int32_t)cc);
                 }
+                if (__ballot(fert) && lane == 0)
+                    sh.fertile[par] = 1;
             }
-            // the pass's children are the next pass's parents
+            // the pass's children are the next pass's parents; a pass whose
+            // children cannot have children under kn is the last one
             __syncthreads();
             const uint32_t created = sh.alloc;
+            const bool more = sh.fertile[par] != 0;
+            if (tid == 0)
+                sh.fertile[par ^ 1] = 0;
             __syncthreads();   // read before the next pass claims slots
-            if (created > node_cap || created == pend)
+            if (created > node_cap || created == pend || !more)
                 break;
             pstart = pend;
             pend = created;
             first = false;
+            par ^= 1;
         }
         const uint32_t used = sh.alloc;
         if (used <= node_cap) {
@@ -1195,9 +1208,10 @@ __global__ __launch_bounds__(256, 7) void grand_decode_kernel(KernelArgs a)
 
 // The same for one launch shape fixed at compile time (256 threads, next
 // power of two of 2L = NI, low table of 2^LB): LDS offsets and loop strides
-// become immediates, which frees scalar registers.
+// become immediates, which frees enough registers for 8 waves per SIMD
+// (64 VGPRs, no spills) -- the most a SIMD holds.
 template <uint32_t NI, uint32_t LB>
-__global__ __launch_bounds__(256, 7) void grand_decode_kernel_fixed(KernelArgs a)
+__global__ __launch_bounds__(256, 8) void grand_decode_kernel_fixed(KernelArgs a)
 {
     __shared__ Shared sh;
     decode_loop<256, NI, LB>(a, sh);
