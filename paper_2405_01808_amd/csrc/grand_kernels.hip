@@ -261,15 +261,17 @@ __device__ void build_buckets(const uint32_t *keys, uint32_t cnt, uint32_t kshif
 }
 
 // First index in [lo, hi) whose cost exceeds x (keys sorted by cost; x
-// below xlim, the bound that keeps x << kshift within 32 bits).
+// below xlim, the bound that keeps x << kshift within 32 bits).  Costs and
+// thresholds are 32-bit: a pattern of at most 1024 flips of cost below
+// 2^15 costs less than 2^25, and thresholds stay below 2^26.
 __device__ inline uint32_t ub_bucket(const uint32_t *keys, Buckets bk, uint32_t kshift,
-                                     int64_t xlim, uint32_t lo, uint32_t hi, int64_t x)
+                                     int32_t xlim, uint32_t lo, uint32_t hi, int32_t x)
 {
     if (x < 0)
         return lo;
     if (x >= xlim)
         return hi;
-    const uint64_t u = (uint64_t)x >> bk.shift;
+    const uint32_t u = (uint32_t)x >> bk.shift;
     if (u >= bk.nb)
         return hi;
     uint32_t a = max(lo, bk.idx[u]), b = min(hi, bk.idx[u + 1]);
@@ -373,8 +375,8 @@ __device__ inline Thr thr_succ(Thr t, uint32_t n)
 __device__ inline uint32_t child_end(const uint32_t *ikey, Buckets ib, uint32_t rl, uint32_t n,
                                      Thr k, int32_t cp)
 {
-    uint32_t A = ub_bucket(ikey, ib, 10, 1ll << 22, rl, n, (int64_t)k.C - 1 - cp);
-    uint32_t B = ub_bucket(ikey, ib, 10, 1ll << 22, A, n, (int64_t)k.C - cp);
+    uint32_t A = ub_bucket(ikey, ib, 10, 1 << 22, rl, n, k.C - 1 - cp);
+    uint32_t B = ub_bucket(ikey, ib, 10, 1 << 22, A, n, k.C - cp);
     uint32_t x = min(B, (uint32_t)max(k.R, 0));
     return max(A, x);
 }
@@ -387,10 +389,10 @@ __device__ inline uint32_t node_end(const uint32_t *lkey, Buckets lb, uint32_t L
                                     int32_t ch, uint32_t h, uint32_t rl, uint32_t ptr)
 {
     // entries before ptr are already checked, and the end never moves back
-    if (ptr >= LB || (int64_t)ch + (lkey[ptr] >> kMaskBits) > (int64_t)k.C)
+    if (ptr >= LB || ch + (int32_t)(lkey[ptr] >> kMaskBits) > k.C)
         return ptr;
-    uint32_t a = ub_bucket(lkey, lb, kMaskBits, 1ll << 19, ptr, LB, (int64_t)k.C - 1 - ch);
-    uint32_t b = ub_bucket(lkey, lb, kMaskBits, 1ll << 19, a, LB, (int64_t)k.C - ch);
+    uint32_t a = ub_bucket(lkey, lb, kMaskBits, 1 << 19, ptr, LB, k.C - 1 - ch);
+    uint32_t b = ub_bucket(lkey, lb, kMaskBits, 1 << 19, a, LB, k.C - ch);
     if (b == a)
         return a;
     if (h != 0)
@@ -412,7 +414,7 @@ __device__ inline uint32_t node_end(const uint32_t *lkey, Buckets lb, uint32_t L
 // Child rank r of a parent with cost cp is admitted by threshold k.
 __device__ inline bool child_admitted(const uint32_t *ikey, uint32_t r, Thr k, int32_t cp)
 {
-    int64_t c = (int64_t)cp + (ikey[r] >> 10);
+    const int32_t c = cp + (int32_t)(ikey[r] >> 10);
     return c < k.C || (c == k.C && (int32_t)r < k.R);
 }
 
@@ -462,29 +464,20 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
         uint32_t pstart = 0, pend = used0, par = 0;
         bool first = true;
         for (;;) {   // one pass per forest level
-            // the parent fields of this lane's slot in the wave's next block
-            // are loaded while the current block is processed (parents are
-            // not written during a pass, except each one's own frontier)
-            uint32_t nx_c = 0, nx_lo = 0, nx_ld = 0;
-            {
-                const uint32_t h = pstart + wid * 64 + lane;
-                if (h < pend) {
-                    const uint4 v = nd.rec[h];
-                    nx_c = v.x;
-                    nx_lo = first ? v.w >> 16 : v.z >> kParBits;
-                    nx_ld = v.y;
-                }
-            }
+            // the record of this lane's slot in the wave's next block is
+            // loaded while the current block is processed (parents are not
+            // written during a pass, except each one's own frontier).  The
+            // load is unconditional, at an index clamped into the
+            // workgroup's store, and its fields are taken only in the next
+            // iteration, so nothing waits for it before then.
+            uint4 nx = nd.rec[min(pstart + wid * 64 + lane, node_cap - 1)];
             for (uint32_t c0 = pstart + wid * 64; c0 < pend; c0 += wstride) {
                 const uint32_t h = c0 + lane;
                 uint32_t cnt = 0, lead = 0;
-                const uint32_t ch = nx_c, lo = nx_lo, ld = nx_ld;
-                if (h + wstride < pend) {
-                    const uint4 v = nd.rec[h + wstride];
-                    nx_c = v.x;
-                    nx_lo = first ? v.w >> 16 : v.z >> kParBits;
-                    nx_ld = v.y;
-                }
+                const uint4 v = nx;
+                nx = nd.rec[min(h + wstride, node_cap - 1)];
+                const uint32_t ch = v.x, ld = v.y;
+                const uint32_t lo = first ? v.w >> 16 : v.z >> kParBits;
                 if (h < pend && lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
                     lead = ld;
                     cnt = child_end(A.ikey, ibk, lo, n, kn, (int32_t)ch) - lo;
@@ -937,20 +930,16 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         const uint32_t wid = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
         const uint32_t fbits = filter_log2(b);
         uint32_t lane_size = 0;
-        // the node fields of this lane's slot in the wave's next block are
-        // loaded while the current block is processed
-        uint32_t nx_ptr = 0, nx_cost = 0, nx_lead = 0, nx_rl = 0;
-        if (wid * 64 + lane < used) {
-            const uint32_t h = wid * 64 + lane;
-            const uint4 v = nd.rec[h];
-            nx_ptr = v.w & 0xFFFFu;
-            nx_cost = v.x;
-            nx_lead = v.y;
-            nx_rl = v.z >> kParBits;
-        }
+        // the record of this lane's slot in the wave's next block is loaded
+        // while the current block is processed (unconditionally, at an
+        // index clamped into the workgroup's store; its fields are taken in
+        // the next iteration)
+        const uint32_t cap_last = a.node_cap - 1;
+        uint4 nx = nd.rec[min(wid * 64 + lane, cap_last)];
         for (uint32_t c0 = wid * 64; c0 < used;) {
             const uint32_t h = c0 + lane;
-            const uint32_t lo = nx_ptr, ch = nx_cost, ld = nx_lead, rl = nx_rl;
+            const uint4 v = nx;
+            const uint32_t lo = v.w & 0xFFFFu, ch = v.x, ld = v.y, rl = v.z >> kParBits;
             uint32_t cnt = 0;
             // the wave's next block comes from a shared counter, so waves
             // that finish early take more blocks
@@ -965,13 +954,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                 }
             }
             cn = (uint32_t)__builtin_amdgcn_readlane((int)cn, 0);
-            if (cn + lane < used) {
-                const uint4 v = nd.rec[cn + lane];
-                nx_ptr = v.w & 0xFFFFu;
-                nx_cost = v.x;
-                nx_lead = v.y;
-                nx_rl = v.z >> kParBits;
-            }
+            nx = nd.rec[min(cn + lane, cap_last)];
             lane_size += cnt;
             bool cand = false;
             if (cnt) {
@@ -1059,8 +1042,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                 int32_t ch = (int32_t)nd.cost(h);
                 if (ch > (int32_t)hc)
                     continue;
-                uint32_t lo = ub_bucket(lkey, lbk, kMaskBits, 1ll << 19, 0, LB, (int64_t)hc - 1 - ch);
-                uint32_t hi = ub_bucket(lkey, lbk, kMaskBits, 1ll << 19, lo, LB, (int64_t)hc - ch);
+                uint32_t lo = ub_bucket(lkey, lbk, kMaskBits, 1 << 19, 0, LB, (int32_t)hc - 1 - ch);
+                uint32_t hi = ub_bucket(lkey, lbk, kMaskBits, 1 << 19, lo, LB, (int32_t)hc - ch);
                 below += lo;
                 if (hi > lo) {
                     int c = colex_cmp(nd, h, hit_h);
