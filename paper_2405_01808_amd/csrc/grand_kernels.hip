@@ -375,10 +375,13 @@ __device__ inline Thr thr_succ(Thr t, uint32_t n)
 __device__ inline uint32_t child_end(const uint32_t *ikey, Buckets ib, uint32_t rl, uint32_t n,
                                      Thr k, int32_t cp)
 {
-    uint32_t A = ub_bucket(ikey, ib, 10, 1 << 22, rl, n, k.C - 1 - cp);
-    uint32_t B = ub_bucket(ikey, ib, 10, 1 << 22, A, n, k.C - cp);
-    uint32_t x = min(B, (uint32_t)max(k.R, 0));
-    return max(A, x);
+    // ranks [A, B) cost exactly C - cp; A is searched for only when that
+    // run is not empty, which is rare
+    const uint32_t B = ub_bucket(ikey, ib, 10, 1 << 22, rl, n, k.C - cp);
+    if (B == rl || cp + (int32_t)(ikey[B - 1] >> 10) != k.C)
+        return B;
+    const uint32_t A = ub_bucket(ikey, ib, 10, 1 << 22, rl, B, k.C - 1 - cp);
+    return max(A, min(B, (uint32_t)max(k.R, 0)));
 }
 
 // End of node h's admitted low-table entries under threshold k: entries with
@@ -391,8 +394,12 @@ __device__ inline uint32_t node_end(const uint32_t *lkey, Buckets lb, uint32_t L
     // entries before ptr are already checked, and the end never moves back
     if (ptr >= LB || ch + (int32_t)(lkey[ptr] >> kMaskBits) > k.C)
         return ptr;
-    uint32_t a = ub_bucket(lkey, lb, kMaskBits, 1 << 19, ptr, LB, k.C - 1 - ch);
-    uint32_t b = ub_bucket(lkey, lb, kMaskBits, 1 << 19, a, LB, k.C - ch);
+    // entries [a, b) cost exactly C - ch; a is searched for only when that
+    // run is not empty, which is rare
+    const uint32_t b = ub_bucket(lkey, lb, kMaskBits, 1 << 19, ptr, LB, k.C - ch);
+    if (b == ptr || ch + (int32_t)(lkey[b - 1] >> kMaskBits) != k.C)
+        return b;
+    const uint32_t a = ub_bucket(lkey, lb, kMaskBits, 1 << 19, ptr, b, k.C - 1 - ch);
     if (b == a)
         return a;
     if (h != 0)
@@ -593,18 +600,22 @@ __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint3
     const uint32_t b0 = min(b, 6u), n0 = 1u << b0;
     uint32_t *src = ((b - b0) & 1) ? ltmp : lkey, *dst = ((b - b0) & 1) ? lkey : ltmp;
     if (tid < 64) {
-        uint32_t key = 0xFFFFFFFFu;
-        if (tid < n0) {
-            uint32_t cost = 0;
-            for (uint32_t k = 0; k < b0; k++)
-                cost += (tid >> k) & 1u ? A.ikey[k] >> 10 : 0u;
-            key = (cost << kMaskBits) | tid;
-        }
-        uint32_t r = 0;
-        for (uint32_t m = 0; m < n0; m++)
-            r += (uint32_t)__builtin_amdgcn_readlane((int)key, (int)m) < key ? 1u : 0u;
+        // the six costs are read at once and selected without branches; the
+        // 64 comparisons are unrolled into four independent counts (lanes
+        // past n0 hold the largest key and count for no one)
+        uint32_t c6[6];
+        for (uint32_t k = 0; k < 6; k++)
+            c6[k] = k < b0 ? A.ikey[k] >> 10 : 0u;
+        uint32_t cost = 0;
+        for (uint32_t k = 0; k < 6; k++)
+            cost += (tid >> k) & 1u ? c6[k] : 0u;
+        const uint32_t key = tid < n0 ? (cost << kMaskBits) | tid : 0xFFFFFFFFu;
+        uint32_t r4[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t m = 0; m < 64; m++)
+            r4[m & 3] += (uint32_t)__builtin_amdgcn_readlane((int)key, (int)m) < key ? 1u : 0u;
         if (tid < n0)
-            src[r] = key;
+            src[(r4[0] + r4[1]) + (r4[2] + r4[3])] = key;
     }
     const uint32_t fbits = filter_log2(b);
     for (uint32_t i = tid; i < (1u << (fbits - 5)); i += bs)
@@ -942,10 +953,13 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             const uint32_t lo = v.w & 0xFFFFu, ch = v.x, ld = v.y, rl = v.z >> kParBits;
             uint32_t cnt = 0;
             // the wave's next block comes from a shared counter, so waves
-            // that finish early take more blocks
+            // that finish early take more blocks; its records are requested
+            // before this block's ranges are computed
             uint32_t cn = 0;
             if (lane == 0)
                 cn = atomicAdd(&sh.next, 64u);
+            cn = (uint32_t)__builtin_amdgcn_readlane((int)cn, 0);
+            nx = nd.rec[min(cn + lane, cap_last)];
             if (h < used) {
                 uint32_t hi = node_end(lkey, lbk, LB, kt, (int32_t)ch, h, rl, lo);
                 if (hi > lo) {
@@ -953,8 +967,6 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                     nd.set_ptr(h, hi);
                 }
             }
-            cn = (uint32_t)__builtin_amdgcn_readlane((int)cn, 0);
-            nx = nd.rec[min(cn + lane, cap_last)];
             lane_size += cnt;
             bool cand = false;
             if (cnt) {
