@@ -474,15 +474,16 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
             // the record of this lane's slot in the wave's next block is
             // loaded while the current block is processed (parents are not
             // written during a pass, except each one's own frontier).  The
-            // load is unconditional, at an index clamped into the
-            // workgroup's store, and its fields are taken only in the next
-            // iteration, so nothing waits for it before then.
-            uint4 nx = nd.rec[min(pstart + wid * 64 + lane, node_cap - 1)];
+            // load is unconditional, at an index clamped to the pass's last
+            // parent (a line the workgroup has just used, so a load past the
+            // end stays in the cache), and its fields are taken only in the
+            // next iteration, so nothing waits for it before then.
+            uint4 nx = nd.rec[min(pstart + wid * 64 + lane, pend - 1)];
             for (uint32_t c0 = pstart + wid * 64; c0 < pend; c0 += wstride) {
                 const uint32_t h = c0 + lane;
                 uint32_t cnt = 0, lead = 0;
                 const uint4 v = nx;
-                nx = nd.rec[min(h + wstride, node_cap - 1)];
+                nx = nd.rec[min(h + wstride, pend - 1)];
                 const uint32_t ch = v.x, ld = v.y;
                 const uint32_t lo = first ? v.w >> 16 : v.z >> kParBits;
                 if (h < pend && lo < n && child_admitted(A.ikey, lo, kn, (int32_t)ch)) {
@@ -943,10 +944,10 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         uint32_t lane_size = 0;
         // the record of this lane's slot in the wave's next block is loaded
         // while the current block is processed (unconditionally, at an
-        // index clamped into the workgroup's store; its fields are taken in
-        // the next iteration)
-        const uint32_t cap_last = a.node_cap - 1;
-        uint4 nx = nd.rec[min(wid * 64 + lane, cap_last)];
+        // index clamped to the last node of the store; its fields are taken
+        // in the next iteration)
+        const uint32_t last = used - 1;
+        uint4 nx = nd.rec[min(wid * 64 + lane, last)];
         for (uint32_t c0 = wid * 64; c0 < used;) {
             const uint32_t h = c0 + lane;
             const uint4 v = nx;
@@ -959,7 +960,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             if (lane == 0)
                 cn = atomicAdd(&sh.next, 64u);
             cn = (uint32_t)__builtin_amdgcn_readlane((int)cn, 0);
-            nx = nd.rec[min(cn + lane, cap_last)];
+            nx = nd.rec[min(cn + lane, last)];
             if (h < used) {
                 uint32_t hi = node_end(lkey, lbk, LB, kt, (int32_t)ch, h, rl, lo);
                 if (hi > lo) {
