@@ -59,6 +59,7 @@ struct Shared {
     uint32_t best_tid;
     uint32_t best_h;
     uint32_t best_l;
+    uint32_t ncand;                  // threads holding a hit of the band's lowest cost
     uint32_t overflow;
     int32_t cmax;
     unsigned long long acc;
@@ -1015,18 +1016,26 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
         cum += band_size;
         if (hc != 0xFFFFFFFFu) {
             const bool cand = best.h != kNone && best.cost == hc;
-            if (tid == 0)
+            if (tid == 0) {
                 sh.best_tid = kNone;
+                sh.ncand = 0;
+                sh.acc = 0;
+            }
             __syncthreads();
-            if (cand)
+            if (cand) {
                 atomicMin(&sh.best_tid, tid);
+                atomicAdd(&sh.ncand, 1u);
+            }
             __syncthreads();
             if (tid == sh.best_tid) {
                 sh.best_h = best.h;
                 sh.best_l = best.l;
             }
+            // a tournament is needed only when several threads hold a hit
+            // of the lowest cost (rare)
+            const bool tie = sh.ncand > 1;
             __syncthreads();
-            for (;;) {   // tournament among equal-cost hits, colex decides
+            for (; tie;) {   // tournament among equal-cost hits, colex decides
                 const uint32_t bh = sh.best_h, bl = sh.best_l;
                 __syncthreads();
                 if (tid == 0)
@@ -1046,10 +1055,8 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             }
             hit_h = sh.best_h;
             hit_l = sh.best_l;
-            // rank: patterns with a smaller (cost, colex) key
-            if (tid == 0)
-                sh.acc = 0;
-            __syncthreads();
+            // rank: patterns with a smaller (cost, colex) key (sh.acc was
+            // cleared before the barriers above)
             unsigned long long below = 0;
             for (uint32_t h = tid; h < used; h += bs) {
                 int32_t ch = (int32_t)nd.cost(h);
