@@ -77,7 +77,7 @@ struct Stage {
     uint32_t *fb;      // first child rank of each slot
     uint32_t *fcost;   // cost of each slot's parent
     uint32_t *flead;   // leading syndrome word of each slot's parent
-    uint32_t *fown;    // slot of child j, for the block's first 64 children
+    uint32_t *fown;    // marks of the parents' first children in a window of 64
 };
 
 // Per-workgroup arrays in dynamic LDS, sized for the launch (lds_layout).
@@ -155,6 +155,19 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x)
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// Inclusive maximum across the 64 lanes of a wave, with the same DPP steps
+// as wave_incl_scan (lanes with no source take 0).
+__device__ inline uint32_t wave_incl_max(uint32_t x)
+{
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
     return x;
 }
 
@@ -426,21 +439,6 @@ __device__ inline bool child_admitted(const uint32_t *ikey, uint32_t r, Thr k, i
     return c < k.C || (c == k.C && (int32_t)r < k.R);
 }
 
-// Slot k of a block of nodes laid end to end: largest k in [lo, cnt) with
-// foff[k] <= j (foff ascending, foff[lo] <= j).
-__device__ inline uint32_t flat_owner(const uint32_t *foff, uint32_t lo, uint32_t cnt, uint32_t j)
-{
-    uint32_t hi = cnt;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (foff[mid] <= j)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // Raise the node store from "every high subset admitted by kE" to those
 // admitted by kwant.  The admitted child ranks of a parent form one
 // contiguous range; children of old parents not admitted by kE are new, and
@@ -511,21 +509,32 @@ __device__ Thr expand_nodes(Shared &sh, const Arr &A, Buckets ibk, const Nodes &
                 S.fcost[lane] = ch;
                 S.flead[lane] = lead;
                 S.foff[lane] = off;
-                // the slot of child j < 64 (a lane's first child)
-                for (uint32_t j = off; j < min(off + cnt, 64u); j++)
-                    S.fown[j] = lane;
-                wave_sync();
-                const uint32_t ncnt = min(64u, pend - c0);
-                uint32_t k = lane < total ? S.fown[lane] : 0;
+                // children are written 64 at a time; the parent of child j
+                // is the last lane whose first child is at or before j: each
+                // parent marks its first child's slot in the window (lane + 1;
+                // a window's other slots hold 0), and a wave maximum scan
+                // carries the marks forward, starting from the previous
+                // window's last parent
                 bool fert = false;
-                for (uint32_t j = lane; j < total; j += 64) {
-                    if (j >= 64)
-                        k = flat_owner(S.foff, k, ncnt, j);
-                    const uint32_t r = S.fb[k] + (j - S.foff[k]);
-                    const uint32_t cc = S.fcost[k] + (A.ikey[r] >> 10);
-                    nd.set(base + j, cc, S.flead[k] ^ A.col0[r], S.fa[k], r + 1, 0, r + 1);
-                    // the next pass tests this child as a parent the same way
-                    fert |= r + 1 < n && child_admitted(A.ikey, r + 1, kn, (int32_t)cc);
+                uint32_t carry = 0;
+                for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+                    S.fown[lane] = 0;
+                    wave_sync();
+                    if (cnt && off >= j0 && off < j0 + 64)
+                        S.fown[off - j0] = lane + 1;
+                    wave_sync();
+                    const uint32_t k1 = wave_incl_max(max(S.fown[lane], lane == 0 ? carry : 0u));
+                    carry = (uint32_t)__builtin_amdgcn_readlane((int)k1, 63);
+                    const uint32_t j = j0 + lane;
+                    if (j < total) {
+                        const uint32_t k = k1 - 1;
+                        const uint32_t r = S.fb[k] + (j - S.foff[k]);
+                        const uint32_t cc = S.fcost[k] + (A.ikey[r] >> 10);
+                        nd.set(base + j, cc, S.flead[k] ^ A.col0[r], S.fa[k], r + 1, 0, r + 1);
+                        // the next pass tests this child as a parent the same way
+                        fert |= r + 1 < n && child_admitted(A.ikey, r + 1, kn, (int32_t)cc);
+                    }
+                    wave_sync();   // the marks are read before the next window clears them
                 }
                 if (__ballot(fert) && lane == 0)
                     sh.fertile[par] = 1;
