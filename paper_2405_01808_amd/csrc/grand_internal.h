@@ -72,7 +72,7 @@ constexpr uint32_t kBucketsPerKey = 1;  // cost buckets per sorted key
 // the low flips' columns, per-slot staging of a block of parents in an
 // expansion pass (one slot per thread; the low table is built in it before
 // the bands start), bucket indexes of the ranked flips and of the low table,
-// the low table (keys and leading syndrome words, 2^b each) and the bitmap
+// the low table (keys and leading syndrome words, 2^b each) and the Bloom
 // filter of its leading words.
 struct LdsLayout {
     uint32_t yhat, s0, ikey, col0, lcol, foff, fa, fb, fcost, flead, fown, iidx, lidx, lkey,
@@ -80,8 +80,8 @@ struct LdsLayout {
 };
 
 // Bits of the low table's leading-word filter: 32 per entry up to 2^11
-// entries (a one-hash bitmap, ~3 % false positives at that load), 2^16 for
-// larger tables.
+// entries (three bits of one 32-bit word per entry, ~0.3 % false positives
+// at that load), 2^16 for larger tables.
 __host__ __device__ inline uint32_t filter_log2(uint32_t low_bits)
 {
     return (low_bits < 11 ? low_bits : 11) + 5;

@@ -30,7 +30,7 @@
 //     whole cost level, or part of one when a level is too large).  For a
 //     fixed node the band's low entries form one contiguous range of the
 //     sorted table, and one of them can have a zero syndrome only if its
-//     leading word equals the node's: a bitmap filter of the table's
+//     leading word equals the node's: a Bloom filter of the table's
 //     leading words rules out most nodes with one LDS read, and the rest
 //     compare their range entry by entry.  The lowest (cost, colex) zero
 //     syndrome of the first band that has one is the answer; its 1-based
@@ -90,14 +90,26 @@ struct Arr {
     Stage st;          // staging of a block, 64 slots per wave
     uint32_t *iidx;    // bucket index of the ranked flips
     uint32_t *lidx;    // bucket index of the low table
-    uint32_t *lfilt;   // bitmap filter of the low table's leading words
+    uint32_t *lfilt;   // Bloom filter of the low table's leading words
 };
 
-// Bit of leading word x in the low table's filter of 2^fbits bits (a
-// multiplicative hash: its top bits depend on every bit of x).
-__device__ inline uint32_t filt_bit(uint32_t x, uint32_t fbits)
+// The low table's filter of its leading words is a blocked Bloom filter of
+// 2^fbits bits in 32-bit words.  A multiplicative hash of word x picks one
+// filter word by its top fbits - 5 bits (bits 21-31 at most) and three bits
+// of that word by hash bits 6-10, 11-15 and 16-20.  Entering x ORs the three
+// bits into the word; x can be in the table only if all three are set.  A
+// test is one LDS read, as with a one-bit bitmap of the same size, and at 32
+// bits per entry a tenth as many words pass it falsely (0.3 % against 3 %).
+struct FiltKey {
+    uint32_t word, mask;
+};
+
+__device__ inline FiltKey filt_key(uint32_t x, uint32_t fbits)
 {
-    return (x * 0x9E3779B1u) >> (32u - fbits);
+    const uint32_t h = x * 0x9E3779B1u;
+    // (a field of width 0 at fbits = 5: the filter's only word)
+    return FiltKey{__builtin_amdgcn_ubfe(h, 37u - fbits, fbits - 5u),
+                   (1u << ((h >> 6) & 31u)) | (1u << ((h >> 11) & 31u)) | (1u << ((h >> 16) & 31u))};
 }
 
 // Node store in the workgroup's HBM slot: one 16-byte record per node, so a
@@ -595,8 +607,8 @@ __device__ inline void keep_best(LaneHit &best, const Nodes &nd, const uint32_t 
 
 // Low table: the 2^b subsets of the b cheapest flips as keys cost <<
 // kMaskBits | mask, ascending (cost, then colex, which is the mask's integer
-// order), with their leading syndrome words and a bitmap filter of those
-// words (one bit each, by filt_bit).  The subsets of the first b0 =
+// order), with their leading syndrome words and a Bloom filter of those
+// words (three bits of one filter word each, by filt_key).  The subsets of the first b0 =
 // min(b, 6) flips are ranked in wave 0's registers: lane l holds subset l
 // and counts the smaller keys with readlane, with no LDS round trip.  Each
 // further flip j then merges the table with itself plus flip j (levels
@@ -682,8 +694,8 @@ __device__ void build_low_table(const Arr &A, const Nodes &nd, uint32_t b, uint3
         const uint32_t msk = lkey[i] & kMaskAll;
         const uint32_t x = sub[msk & (nlo - 1)] ^ sub[nlo + (msk >> blo)];
         ls0[i] = x;
-        const uint32_t fb = filt_bit(x, fbits);
-        atomicOr(&A.lfilt[fb >> 5], 1u << (fb & 31u));
+        const FiltKey fk = filt_key(x, fbits);
+        atomicOr(&A.lfilt[fk.word], fk.mask);
     }
 }
 
@@ -981,11 +993,11 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
             lane_size += cnt;
             bool cand = false;
             if (cnt) {
-                const uint32_t fb = filt_bit(ld, fbits);
-                cand = (A.lfilt[fb >> 5] >> (fb & 31u)) & 1u;
+                const FiltKey fk = filt_key(ld, fbits);
+                cand = (A.lfilt[fk.word] & fk.mask) == fk.mask;
             }
-            // the filter's hits (false positives and real matches, a few per
-            // block): the whole wave compares each one's range, 64 entries
+            // the filter's hits (false positives and real matches, about one
+            // per ten blocks): the whole wave compares each one's range, 64 entries
             // per step, and verifies the entries whose leading words match
             for (unsigned long long cm = __ballot(cand); cm; cm &= cm - 1) {
                 const int k = __builtin_ctzll(cm);

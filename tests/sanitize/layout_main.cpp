@@ -86,9 +86,10 @@ int main()
                 EXPECT(L.ltmp + ni <= staging_end);   // the cut-off's symbol scores
                 // alignment of the low table
                 EXPECT(L.lkey % 2 == 0);
-                // the leading-word filter: filt_bit gives filter_log2(b)
-                // bits, so word fb >> 5 lies in the filter
-                EXPECT(filter_log2(b) >= 5 && filter_log2(b) <= 32);
+                // the leading-word filter: filt_key takes the word index
+                // from hash bits 21-31 at most (fbits - 5 of them), above
+                // the bit positions' hash bits 6-20
+                EXPECT(filter_log2(b) >= 5 && filter_log2(b) <= 16);
             }
         }
     }
