@@ -997,7 +997,7 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                 cand = (A.lfilt[fk.word] & fk.mask) == fk.mask;
             }
             // the filter's hits (false positives and real matches, about one
-            // per ten blocks): the whole wave compares each one's range, 64 entries
+            // per two blocks): the whole wave compares each one's range, 64 entries
             // per step, and verifies the entries whose leading words match
             for (unsigned long long cm = __ballot(cand); cm; cm &= cm - 1) {
                 const int k = __builtin_ctzll(cm);
