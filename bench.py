@@ -46,7 +46,6 @@ SERVE_BATCH = 256                    # requests per server launch at most
 HW_QUEUES = "16"                     # HIP hardware queues for this process (HIP's default is 4)
 COPY_BYTES = 256 << 20               # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grand_decode_kernel_polar128_16qam_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_01808_amd", "csrc", "grand_kernels.hip")
 # oracle samples (bounded CPU work) and parity samples per workload
 CPU_SAMPLES = {"polar32_qpsk": 1000, "uneven_mix": 256, "polar1024_256qam": 8,
                "serving_mix": 500}
@@ -58,13 +57,14 @@ def log(*a):
 
 def measured_traffic():
     """HBM bytes per launch of the decode kernel from the committed counter
-    runs, or None when the kernel source has changed since they were taken."""
-    import hashlib
+    runs, or None when the kernel's sources or build flags have changed since
+    they were taken."""
     import re
     try:
         text = open(TRAFFIC_FILE).read()
         rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        from paper_2405_01808_amd.build import kernel_source_sha256
+        src = kernel_source_sha256()
     except (OSError, AttributeError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != src:

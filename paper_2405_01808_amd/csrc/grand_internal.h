@@ -141,6 +141,9 @@ inline uint32_t items_pow2(uint32_t n, uint32_t M)
 // workgroup takes indices until one is past the batch, so the counter
 // advances by exactly njobs + grid.
 int launch_decode(const KernelArgs &a, uint32_t grid, uint32_t block, void *stream);
+// The same for the N = 128 16-QAM shape (256 threads, ni = 64, low_bits = 9),
+// whose kernel is built in its own file; lds = dynamic LDS bytes.
+int launch_decode_n128(const KernelArgs &a, uint32_t grid, uint32_t lds, void *stream);
 // Zero n 64-bit counters with a kernel (graph-safe, unlike a memset node).
 int launch_zero(unsigned long long *p, uint32_t n, void *stream);
 
