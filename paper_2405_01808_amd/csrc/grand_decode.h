@@ -15,13 +15,16 @@
 //     yields the Gray bit whose flip moves to the near neighbour on the
 //     received value's side (reversed at the constellation edge) with cost
 //     d = 4096 - sigma * delta.  Flips are ranked by (cost, bit position)
-//     with a bitonic sort (Step 2).
+//     (Step 2): each of up to 256 keys counts the keys below it, a bitonic
+//     sort ranks more.
 //  2. Hard-word syndrome s(yhat) = H yhat^T (Algorithm 1): AND of packed
 //     rows with yhat, parity per 32-bit word, then a wavefront ballot folds
 //     the words of a row -- the log2 N addition tree of pMult.
 //  3. Patterns (Steps 4-5): a pattern T splits into T_l, a subset of the b
 //     cheapest flips, and T_h, a subset of the others.  The 2^b low subsets
-//     are tabulated sorted by (cost, colex), built by b merge-path merges.
+//     are tabulated sorted by (cost, colex): the subsets of the first six
+//     are ranked in registers, then each further flip merges the table with
+//     itself shifted by that flip (merge path).
 //     The high subsets admitted so far ("nodes") form a forest: each node
 //     adds one rank above its parent's largest.  Pattern (h, l) has syndrome
 //     S_h + LS_l with S_h = s(yhat) + the node's columns, so checking it is
