@@ -12,7 +12,7 @@ namespace grand {
 
 int launch_decode_n128(const KernelArgs &a, uint32_t grid, uint32_t lds, void *stream)
 {
-    void (*fn)(KernelArgs) = grand_decode_kernel_fixed<64, 9>;
+    void (*fn)(KernelArgs) = grand_decode_kernel_fixed<64, 9, true>;   // node_end's exits as selects
     if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds) != hipSuccess)
         return -3;
