@@ -756,7 +756,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK,
                      "unit": "int32 lane-ops/s", "frac": achieved / ALU_PEAK,
                      "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
-                     "kernel": "grand_decode_kernel_fixed<64, 9>",
+                     "kernel": "grand_decode_kernel_fixed<64, 9, true>",
                      "work": f"{ops_per_check:.3f} lane-ops ((mean w {sw['mean_w']:.3f} + 1) x "
                              f"ceil(64/32)) x {int(sum_q)} useful checks (sum of q) per launch",
                      "avg_launch_ms": avg_launch_s * 1e3,
