@@ -4,7 +4,9 @@
 // optimizer (the flag is in build.py): the optimizer wraps each single-lane
 // LDS claim in lane-counting code, and this shape ran 4.7 % faster without
 // it, with identical results, while the N = 1024 shape ran 6 % slower, so
-// the other shapes keep the default.
+// the other shapes keep the default.  The kernel also takes the range end's
+// early exits as selects (node_end's SelectExits, 2 % faster here and no
+// faster in the other shapes).
 
 #include "grand_decode.h"
 
