@@ -152,6 +152,39 @@ def test_edge_cases(gpu):
     assert_parity(jobs, g, o, label="edge cases")
 
 
+def test_n128_16qam_kernel_on_boundaries_and_ties(gpu):
+    """The N = 128 16-QAM launch shape has a kernel of its own (its own build
+    flags, range ends with select exits).  384 words, more than the device
+    has compute units, so the batch keeps 256-thread workgroups and that
+    kernel: exact decision boundaries (zero costs), equal costs everywhere,
+    noise-free and noisy words, under caps 1, 2, 777 and 2^16."""
+    rng = np.random.default_rng(11)
+    code = w.polar_code(128, 64)
+    jobs = []
+    for _ in range(24):
+        c = code.encode(rng.integers(0, 2, 64, dtype=np.uint8))
+        pts = w.modulate(c, 16).astype(np.float32).reshape(-1)
+        for variant in range(4):
+            rx = pts.copy()
+            if variant == 1:      # every third value on a decision boundary
+                rx[::3] = np.round(rx[::3]) - np.sign(rx[::3])
+            if variant == 2:      # equal costs everywhere
+                rx = (pts * 0.5).astype(np.float32)
+            if variant == 3:
+                rx = rx + rng.normal(0, 0.7, rx.shape).astype(np.float32)
+            for cap in (1, 2, 777, 1 << 16):
+                jobs.append(w.Job(N=128, K=64, M=16, ebn0_db=0.0, noise_var=1.0, cap=cap,
+                                  rx=rx.astype(np.float32), cw=c))
+    assert len(jobs) > 256
+    say(f"n128 boundaries: {len(jobs)} words")
+    g = gpu_batch(jobs)
+    o = oracle_results(jobs)
+    assert_parity(jobs, g, o, label="n128 boundaries")
+    gcw, gq, gab, gst, gchk = g
+    assert (gst == 0).all()
+    assert (gchk >= gq).all()
+
+
 def test_invalid_rx_reports_status(gpu):
     jobs = w.jobs_from_spec("bad", seed=1, count=4, cap=100, Ns=(32,), Ms=(4,),
                             ebn0=("fixed", 3.0))
