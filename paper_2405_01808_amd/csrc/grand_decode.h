@@ -1132,7 +1132,15 @@ __device__ uint32_t decode_one(const KernelArgs &a, Shared &sh, const Arr &A, ui
                         below += hit_l - lo;
                 }
             }
-            atomicAdd(&sh.acc, below);
+            {   // the wave's sum, then one atomic per wave (a thread counts at
+                // most 2^15 nodes of at most 2^13 entries, below 2^28, so the
+                // wave sums of both halves fit in 32 bits).  An atomic of every
+                // thread on the one address would run lane by lane.
+                const uint32_t l16 = wave_incl_scan((uint32_t)below & 0xFFFFu);
+                const uint32_t h16 = wave_incl_scan((uint32_t)(below >> 16));
+                if (lane_id() == 63)
+                    atomicAdd(&sh.acc, ((unsigned long long)h16 << 16) + l16);
+            }
             __syncthreads();
             q = sh.acc + 1;
             if (q > cap) {
